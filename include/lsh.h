@@ -1,0 +1,219 @@
+/*
+ * lsh.h -- C ABI of liblsh, count-sketch LSH hashing and indexing on MI355X.
+ *
+ * Implements, on one gfx950 GPU, the hashcode generation and index
+ * construction of Verma & Pratap, "Faster and Space Efficient Indexing for
+ * Locality Sensitive Hashing":
+ *   - CS-E2LSH / CS-SRP   (Section 4.1 Definition CS_Eucl_LSH, Section 5.1
+ *                          Definition cs_consine_lsh): count-sketch projection
+ *                          (Section 3.2 Definition def_cs, Eq. eq_cs), then
+ *                          floor((sqrt(m) y + b)/w) or sgn(y);
+ *   - HCS-E2LSH / HCS-SRP (Section 4.2 Definition HCS_Eucl_LSH, Eq.
+ *                          eq_hca_eucl_lsh; Section 5.2 Definition
+ *                          hcs_consine_lsh): higher-order count sketch of the
+ *                          reshaped tensor (Definition def_hcs, Eq. eqhcs);
+ *   - dense E2LSH / SRP   (Section 3.1, Eq. datar_lsh and Definition srp): the
+ *                          O(md) baseline, y = x R;
+ *   - the (m, tau) index  (Section 3.1): the K codes of each of L tables form a
+ *                          bucket key, every point is stored in its bucket;
+ *   - the query           (Section 3.1 and Section 6): union of the probed
+ *                          buckets, re-ranked by exact distance, top-k.
+ *
+ * Conventions for every call:
+ *   - All array arguments are DEVICE pointers owned by the caller unless marked
+ *     "host".  The library never allocates or frees device memory; scratch
+ *     space comes in through explicit workspace arguments whose size the
+ *     matching *_bytes() function returns.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
+ *     default stream).  Nothing blocks except argument validation on the host.
+ *   - Return value: LSH_OK, or a negative lsh_status with a message available
+ *     from lsh_last_error() (thread-local).  On error nothing was enqueued.
+ *   - n = 0 is a valid no-op wherever n appears.
+ *   - Hashcode length m = K * L: one sketch of m components per point, split
+ *     into L tables of K consecutive components (table t owns components
+ *     [tK, tK+K)).
+ */
+#ifndef LSH_H
+#define LSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LSH_OK = 0,
+    LSH_EINVAL = -1, /* an argument is out of range or inconsistent */
+    LSH_ENOMEM = -2, /* a workspace or index buffer is smaller than required */
+    LSH_EHIP = -3,   /* the HIP runtime reported an error (message has it) */
+    LSH_ERANGE = -5  /* a size exceeds what the index format can hold */
+} lsh_status;
+
+typedef enum { LSH_E2LSH = 0, LSH_SRP = 1 } lsh_family;
+
+typedef enum {
+    LSH_F32 = 0,        /* IEEE binary32 */
+    LSH_BF16 = 1,       /* bfloat16 bit patterns, value = row_scale[i] * bf16 */
+    LSH_FP8_E4M3FN = 2  /* OCP FP8 E4M3FN bit patterns, value = row_scale[i] * fp8 */
+} lsh_dtype;
+
+/* A set of n points of dimension d, row-major: point i, coordinate j is
+ * element x[i*ld + j].  row_scale is required for LSH_BF16 / LSH_FP8_E4M3FN
+ * and must be NULL for LSH_F32.  x must stay valid until the enqueued work
+ * completes. */
+typedef struct lsh_points {
+    const void *x;
+    int32_t dtype;           /* lsh_dtype */
+    const float *row_scale;  /* [n] or NULL */
+    int64_t n;
+    int32_t d;
+    int64_t ld;              /* >= d, in elements */
+} lsh_points;
+
+/* Discretisation and table layout. */
+typedef struct lsh_disc {
+    int32_t family;   /* lsh_family */
+    int32_t m;        /* hashcode length; must equal K * L */
+    int32_t K;        /* components per table, 1..64 (SRP keys hold K bits) */
+    int32_t L;        /* number of tables, >= 1 */
+    float w;          /* E2LSH bucket width, w > 0 (ignored for SRP) */
+    const float *b;   /* [m] shifts in [0, w) (E2LSH only; NULL for SRP) */
+    int32_t recheck;  /* 0: FP32 result as computed.  1: every component whose
+                         FP32 value lies within a rigorous bound of its
+                         rounding error from a bin edge (E2LSH) or from zero
+                         (SRP) is recomputed in FP64 in ascending coordinate
+                         order, so codes equal those of an FP64 evaluation.
+                         CS/HCS only; needs d <= 32768. */
+} lsh_disc;
+
+/* Outputs.  Any pointer may be NULL to skip that output. */
+typedef struct lsh_out {
+    uint64_t *keys;     /* [L][key_ld]: bucket key of point i in table t at keys[t*key_ld + i].
+                           SRP: bit r = sign bit of component tK + r.
+                           E2LSH: 64-bit digest of the K codes of the table,
+                           computed as specified under "E2LSH bucket key" below. */
+    int64_t key_ld;     /* 0 means n */
+    int32_t *codes;     /* [n][m] E2LSH codes (int32, saturated) or SRP bits (0/1) */
+    float *proj;        /* [n][m] projection y before any sqrt(m) scale, row scale applied */
+    uint64_t *counters; /* [4], accumulated (not reset) by the call:
+                           [0] components recomputed in FP64 (recheck = 1),
+                           [1] of those, components whose code changed,
+                           [2] E2LSH codes that saturated to the int32 range,
+                           [3] reserved, left unchanged */
+} lsh_out;
+
+/*
+ * E2LSH bucket key.  For table t with codes c_0..c_{K-1} (int32):
+ *   narrow (every c_r in [-128,127]): words of 8 codes, code r is byte (r mod 8)
+ *       (two's complement) of word floor(r/8);
+ *   wide: words of 2 codes, code r is the 32-bit half (r mod 2) of word floor(r/2);
+ *   h = F(2t + wide); for each word W in order: h = F(h XOR W); key = h;
+ *   F = the SplitMix64 finaliser (Steele, Lea and Flood 2014): z ^= z>>30;
+ *       z *= 0xbf58476d1ce4e5b9; z ^= z>>27; z *= 0x94d049bb133111eb; z ^= z>>31.
+ */
+
+/* ---------------------------------------------------------------- hashing */
+
+/* Workspace bytes for lsh_hash_cs / lsh_hash_hcs (0 unless recheck = 1). */
+size_t lsh_hash_workspace_bytes(int32_t d, int32_t m, int32_t recheck);
+
+/* CS-E2LSH / CS-SRP of every point (Definitions CS_Eucl_LSH and
+ * cs_consine_lsh): y_l = sum over j with h[j] = l of s[j] * x_j, then the
+ * family's discretisation, codes and keys.
+ *   h: [d] bins in [0, m); s: [d] signs, each +1 or -1.
+ * Requires m <= 32768.  EINVAL on bad shapes, ENOMEM if ws_bytes is short. */
+lsh_status lsh_hash_cs(const lsh_points *pts, const uint32_t *h, const int8_t *s,
+                       const lsh_disc *disc, const lsh_out *out, void *workspace,
+                       size_t ws_bytes, void *stream);
+
+/* HCS-E2LSH / HCS-SRP (Definitions HCS_Eucl_LSH and hcs_consine_lsh).  The
+ * point is read as an N-order tensor d_1 x ... x_N (first mode fastest,
+ * zero-padded at the end when d < prod d_k, as in Section 6) and sketched
+ * with per-mode hashes h_k:[d_k] -> [m_k] and signs s_k; component
+ * l = l_1 + l_2 m_1 + l_3 m_1 m_2 + ... of vec(HCS).
+ *   N: 1..8; d_k, m_k: host arrays [N]; prod m_k must equal disc->m.
+ *   h_k, s_k: device arrays holding h_1..h_N (s_1..s_N) back to back
+ *   (sum d_k entries). */
+lsh_status lsh_hash_hcs(const lsh_points *pts, int32_t N, const int32_t *d_k, const int32_t *m_k,
+                        const uint32_t *h_k, const int8_t *s_k, const lsh_disc *disc,
+                        const lsh_out *out, void *workspace, size_t ws_bytes, void *stream);
+
+/* Dense E2LSH / SRP (Section 3.1): y = x R on FP32 matrix cores, then
+ * floor((y + b)/w) (no sqrt(m) scale) or sgn(y).  R: [d][m] row-major FP32.
+ * F32 points only; recheck must be 0. */
+lsh_status lsh_hash_dense(const lsh_points *pts, const float *R, const lsh_disc *disc,
+                          const lsh_out *out, void *stream);
+
+/* ------------------------------------------------------------------ index */
+
+typedef struct lsh_index lsh_index; /* host-side descriptor; arrays live in caller memory */
+
+/* Device view of a built index (Section 3.1: bucket of each key per table).
+ * Table t: distinct keys ukeys[t*n + u] ascending for u < nuniq[t]; bucket u
+ * holds ids sorted_ids[t*n + offs[t*(n+1) + u] .. t*n + offs[t*(n+1) + u + 1]),
+ * ascending. */
+typedef struct lsh_index_view {
+    int64_t n;
+    int32_t L;
+    int64_t id_base;
+    uint32_t *sorted_ids;  /* [L][n] */
+    uint64_t *ukeys;       /* [L][n] (first nuniq[t] valid) */
+    uint32_t *offs;        /* [L][n+1] (first nuniq[t]+1 valid) */
+    int64_t *nuniq;        /* [L] */
+} lsh_index_view;
+
+/* Bytes of device memory an index over n points and L tables occupies. */
+size_t lsh_index_bytes(int64_t n, int32_t L);
+/* Bytes of temporary workspace lsh_build_index needs. */
+size_t lsh_build_workspace_bytes(int64_t n, int32_t L);
+
+/* Group the n points into buckets, per table: a stable 64-bit LSD radix sort
+ * of (key, id) with ids = id_base + i, then distinct keys and bucket offsets.
+ * keys: [L][key_ld] (key_ld 0 means n).  mem: index storage (lsh_index_bytes,
+ * 256-byte aligned), ws: workspace (lsh_build_workspace_bytes, 256-byte
+ * aligned; free for reuse once the enqueued work completes).  On success
+ * *out receives a descriptor (release with lsh_index_free).
+ * ERANGE if id_base + n exceeds 2^32 - 1. */
+lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int64_t n, int32_t L,
+                           int64_t id_base, void *mem, size_t mem_bytes, void *workspace,
+                           size_t ws_bytes, lsh_index **out, void *stream);
+
+/* Fill *view with the device arrays of idx (host call, no GPU work). */
+lsh_status lsh_index_get_view(const lsh_index *idx, lsh_index_view *view);
+
+/* Release the host descriptor (device memory belongs to the caller). */
+void lsh_index_free(lsh_index *idx);
+
+/* ------------------------------------------------------------------ query */
+
+/* Answer nq queries against nseg index segments (1..16) with the same L
+ * (Section 3.1: union of the buckets holding each query key; Section 6:
+ * exact re-rank, top-k).
+ *   base: every indexed point addressed by global id (row id of base).
+ *   Q: the queries (any lsh_dtype); qkeys: [L][qkey_ld] keys of the queries,
+ *      as produced by the lsh_hash_* call that built the index keys.
+ *   Candidates with id >= id_watermark are ignored.
+ *   metric: LSH_E2LSH = Euclidean distance, LSH_SRP = 1 - cos (cos = 0 when a
+ *   norm is 0).  Output per query: ids[q*k + r] (int64, -1 pad), score[q*k + r]
+ *   (FP32, +inf pad) in ascending (score, id) order; ncand[q] = number of
+ *   distinct candidates (any output may be NULL except ids).  k: 1..64. */
+lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, const lsh_points *base,
+                     const lsh_points *Q, const uint64_t *qkeys, int64_t qkey_ld, int32_t k,
+                     int64_t id_watermark, int32_t metric, int64_t *ids, float *score,
+                     int32_t *ncand, void *stream);
+
+/* ------------------------------------------------------------------ misc */
+
+/* Message for the last non-OK status returned on this thread. */
+const char *lsh_last_error(void);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int32_t lsh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSH_H */

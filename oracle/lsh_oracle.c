@@ -188,6 +188,11 @@ void orc_disc_e2lsh(const double *y, int64_t n, int32_t m, const float *b, float
             double t = alpha * y[i * (int64_t)m + l];
             double v = t + (double)b[l];
             double c = floor(v / ww);
+            /* codes are stored as int32; values beyond its range saturate */
+            if (c < -2147483648.0)
+                c = -2147483648.0;
+            if (c > 2147483647.0)
+                c = 2147483647.0;
             codes[i * (int64_t)m + l] = (int32_t)c;
             if (near_edge) {
                 double dist = fabs(v - ww * nearbyint(v / ww));

@@ -1,0 +1,476 @@
+// Query probe and exact re-rank on gfx950.
+//
+// For each query (Section 3.1): look up its key in every table of every
+// index segment, take the union of the bucket contents (ids below the
+// watermark), score every distinct candidate by its exact distance to the
+// query (Euclidean, or 1 - cos), and keep the k best by (score, id)
+// (Section 6 retrieves the top-k this way).
+//
+// One workgroup per query.  Every bucket is an ascending id list, so the
+// union is processed in windows of the id space that hold at most kCap
+// (bucket, id) entries: each window is gathered into LDS, sorted and
+// deduplicated, its distinct ids are scored (one wave per candidate row,
+// coalesced loads), and the window's (score, id) pairs are merged with the
+// running top-k by a bitonic sort of 64-bit (score bits, id) keys.  Memory
+// is bounded whatever the bucket sizes.
+
+#include <math.h>
+
+#include "lsh_internal.h"
+
+namespace lsh {
+
+constexpr int kQThreads = 256;
+constexpr int kQWaves = kQThreads / kWave;
+constexpr int kCap = 2048;        // (bucket, id) entries per window
+constexpr int kMaxK = 64;
+constexpr int kSortCap = 4096;    // >= next pow2 of kCap + kMaxK
+constexpr int kMaxSeg = 16;
+constexpr int kMaxLists = 1024;   // nseg * L
+
+struct QSeg {
+    const uint32_t *ids;
+    const uint64_t *ukeys;
+    const uint32_t *offs;
+    const int64_t *nuniq;
+    int64_t n;
+};
+
+struct QueryArgs {
+    QSeg seg[kMaxSeg];
+    int32_t nseg, L;
+    // base points
+    const void *bx;
+    int32_t bdt;
+    const float *bscale;
+    int64_t bld;
+    int64_t bn;
+    // queries
+    const void *qx;
+    int32_t qdt;
+    const float *qscale;
+    int64_t qld;
+    int32_t d;
+    const uint64_t *qkeys;
+    int64_t qkey_ld;
+    int32_t k;
+    uint32_t watermark; // ids >= watermark are ignored (clamped to 2^32-1)
+    int32_t metric;
+    int64_t *ids;
+    float *score;
+    int32_t *ncand;
+};
+
+__device__ __forceinline__ float load_val(const void *x, int dt, const float *scale, int64_t row,
+                                          int64_t ld, int32_t j)
+{
+    float sc = scale ? scale[row] : 1.0f;
+    if (dt == LSH_F32)
+        return ((const float *)x)[row * ld + j];
+    if (dt == LSH_BF16)
+        return sc * __uint_as_float((uint32_t)((const uint16_t *)x)[row * ld + j] << 16);
+    uint32_t b = ((const uint8_t *)x)[row * ld + j];
+    float mag = __uint_as_float((b & 0x7fu) << 20) * 0x1.0p120f;
+    return sc * __uint_as_float(__float_as_uint(mag) | ((b & 0x80u) << 24));
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *a, uint32_t lo, uint32_t hi,
+                                                     uint32_t v)
+{
+    while (lo < hi) {
+        uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Bitonic sort of n (power of two) 64-bit keys in LDS, ascending, whole block.
+__device__ void block_bitonic(uint64_t *s, int n)
+{
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    uint64_t x = s[i], y = s[ixj];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        s[i] = y;
+                        s[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *red)
+{
+    v = wave_sum(v);
+    if (lane_id() == 0)
+        red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    uint32_t t = 0;
+    for (int w = 0; w < kQWaves; ++w)
+        t += red[w];
+    __syncthreads();
+    return t;
+}
+
+// Exclusive prefix of v over the block (thread order); *total gets the sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, uint32_t *total)
+{
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t u = __shfl_up(incl, o, kWave);
+        if (lane >= o)
+            incl += u;
+    }
+    if (lane == kWave - 1)
+        red[wid] = incl;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int w = 0; w < kQWaves; ++w) {
+        off += w < wid ? red[w] : 0;
+        tot += red[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
+__global__ __launch_bounds__(kQThreads) void query_kernel(QueryArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    float *qv = (float *)lds;                                          // [d]
+    uint32_t *lst_start = (uint32_t *)(lds + ((a.d * 4 + 15) & ~15));  // [kMaxLists]
+    uint32_t *lst_cur = lst_start + kMaxLists;                         // [kMaxLists]
+    uint32_t *lst_end = lst_cur + kMaxLists;                           // [kMaxLists]
+    uint32_t *lst_pre = lst_end + kMaxLists;                           // [kMaxLists + 1]
+    uint32_t *lst_take = lst_pre + kMaxLists + 1;                      // [kMaxLists]
+    uint64_t *sbuf = (uint64_t *)(((uintptr_t)(lst_take + kMaxLists) + 15) & ~(uintptr_t)15); // [kSortCap]
+    uint64_t *topk = sbuf + kSortCap;                                  // [kMaxK]
+    uint32_t *cand = (uint32_t *)(topk + kMaxK);                       // [kCap]
+    __shared__ uint32_t red[kQWaves];
+    __shared__ float s_qnorm;
+    __shared__ int s_kcur;
+    __shared__ uint32_t s_ncand, s_hi, s_wcount, s_ucount;
+
+    const int q = blockIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const int nl = a.nseg * a.L;
+
+    // query row -> LDS, and its norm
+    float part = 0.0f;
+    for (int j = tid; j < a.d; j += kQThreads) {
+        float v = load_val(a.qx, a.qdt, a.qscale, q, a.qld, j);
+        qv[j] = v;
+        part += v * v;
+    }
+    part = wave_sum(part);
+    if (lane == 0)
+        red[wid] = __float_as_uint(part);
+    __syncthreads();
+    if (tid == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < kQWaves; ++w)
+            t += __uint_as_float(red[w]);
+        s_qnorm = sqrtf(t);
+        s_kcur = 0;
+        s_ncand = 0;
+    }
+
+    // probe: bucket of the query key in every (segment, table)
+    for (int li = tid; li < nl; li += kQThreads) {
+        int sg = li / a.L, t = li % a.L;
+        const QSeg &S = a.seg[sg];
+        uint64_t key = a.qkeys[(int64_t)t * a.qkey_ld + q];
+        const uint64_t *uk = S.ukeys + (int64_t)t * S.n;
+        int64_t lo = 0, hi = S.nuniq[t];
+        while (lo < hi) {
+            int64_t mid = lo + ((hi - lo) >> 1);
+            if (uk[mid] < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        uint32_t st = 0, en = 0;
+        if (lo < S.nuniq[t] && uk[lo] == key) {
+            const uint32_t *of = S.offs + (int64_t)t * (S.n + 1);
+            st = of[lo];
+            en = of[lo + 1];
+            // ids of a bucket ascend: drop the tail at or above the watermark
+            en = lower_bound_u32(S.ids + (int64_t)t * S.n, st, en, a.watermark);
+        }
+        lst_start[li] = st;
+        lst_cur[li] = st;
+        lst_end[li] = en;
+    }
+    __syncthreads();
+
+    const float qn = s_qnorm;
+    while (true) {
+        // remaining entries
+        uint32_t rem = 0;
+        for (int li = tid; li < nl; li += kQThreads)
+            rem += lst_end[li] - lst_cur[li];
+        rem = block_sum_u32(rem, red);
+        if (rem == 0)
+            break;
+        // window [.., hi): all remaining if they fit, else the largest id bound
+        // whose entry count fits kCap (found by bisection on the id value)
+        if (tid == 0)
+            s_hi = 0xffffffffu;
+        __syncthreads();
+        if (rem > kCap) {
+            uint32_t lo_v = 0, hi_v = 0xffffffffu; // count(lo_v) <= kCap < count(hi_v)
+            while (hi_v - lo_v > 1) {
+                uint32_t mid = lo_v + ((hi_v - lo_v) >> 1);
+                uint32_t c = 0;
+                for (int li = tid; li < nl; li += kQThreads) {
+                    int sg = li / a.L, t = li % a.L;
+                    const uint32_t *ids = a.seg[sg].ids + (int64_t)t * a.seg[sg].n;
+                    c += lower_bound_u32(ids, lst_cur[li], lst_end[li], mid) - lst_cur[li];
+                }
+                c = block_sum_u32(c, red);
+                if (c <= kCap)
+                    lo_v = mid;
+                else
+                    hi_v = mid;
+            }
+            if (tid == 0)
+                s_hi = lo_v; // >= one id beyond the smallest remaining: progress
+            __syncthreads();
+        }
+        const uint32_t hiv = s_hi;
+        for (int li = tid; li < nl; li += kQThreads) {
+            int sg = li / a.L, t = li % a.L;
+            const uint32_t *ids = a.seg[sg].ids + (int64_t)t * a.seg[sg].n;
+            uint32_t e = hiv == 0xffffffffu ? lst_end[li]
+                                            : lower_bound_u32(ids, lst_cur[li], lst_end[li], hiv);
+            lst_take[li] = e - lst_cur[li];
+        }
+        __syncthreads();
+        {
+            // prefix of the per-list counts: thread owns a contiguous run of lists
+            const int per = (nl + kQThreads - 1) / kQThreads;
+            const int l0 = tid * per, l1 = l0 + per < nl ? l0 + per : nl;
+            uint32_t mine = 0;
+            for (int li = l0; li < l1; ++li)
+                mine += lst_take[li];
+            uint32_t tot;
+            uint32_t run = block_excl_scan(mine, red, &tot);
+            for (int li = l0; li < l1; ++li) {
+                lst_pre[li] = run;
+                run += lst_take[li];
+            }
+            if (tid == 0) {
+                lst_pre[nl] = tot;
+                s_wcount = tot;
+            }
+        }
+        __syncthreads();
+        const uint32_t wc = s_wcount;
+        int p2 = 1;
+        while (p2 < (int)wc)
+            p2 <<= 1;
+        // gather the window's ids
+        for (uint32_t e = tid; e < (uint32_t)p2; e += kQThreads) {
+            uint64_t v = ~0ull;
+            if (e < wc) {
+                int lo = 0, hi = nl; // list holding entry e: last li with pre[li] <= e
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (lst_pre[mid] <= e)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                while (lst_take[lo] == 0 || lst_pre[lo] + lst_take[lo] <= e)
+                    ++lo;
+                int sg = lo / a.L, t = lo % a.L;
+                v = a.seg[sg].ids[(int64_t)t * a.seg[sg].n + lst_cur[lo] + (e - lst_pre[lo])];
+            }
+            sbuf[e] = v;
+        }
+        __syncthreads();
+        for (int li = tid; li < nl; li += kQThreads)
+            lst_cur[li] += lst_take[li];
+        block_bitonic(sbuf, p2);
+        {
+            // distinct ids, compacted in order: thread owns a contiguous run
+            const int per = (p2 + kQThreads - 1) / kQThreads;
+            const int e0 = tid * per, e1 = e0 + per < (int)wc ? e0 + per : (int)wc;
+            uint32_t mine = 0;
+            for (int e = e0; e < e1; ++e)
+                mine += (e == 0 || sbuf[e] != sbuf[e - 1]);
+            uint32_t tot;
+            uint32_t pos = block_excl_scan(mine, red, &tot);
+            for (int e = e0; e < e1; ++e)
+                if (e == 0 || sbuf[e] != sbuf[e - 1])
+                    cand[pos++] = (uint32_t)sbuf[e];
+            if (tid == 0) {
+                s_ucount = tot;
+                s_ncand += tot;
+            }
+        }
+        __syncthreads();
+        const uint32_t uc = s_ucount;
+        // score: one wave per candidate row
+        for (uint32_t c = wid; c < uc; c += kQWaves) {
+            const int64_t row = cand[c];
+            float acc = 0.0f, xx = 0.0f;
+            for (int j = lane; j < a.d; j += kWave) {
+                float xv = load_val(a.bx, a.bdt, a.bscale, row, a.bld, j);
+                if (a.metric == LSH_E2LSH) {
+                    float df = qv[j] - xv;
+                    acc = fmaf(df, df, acc);
+                } else {
+                    acc = fmaf(qv[j], xv, acc);
+                    xx = fmaf(xv, xv, xx);
+                }
+            }
+            acc = wave_sum(acc);
+            xx = wave_sum(xx);
+            float sc;
+            if (a.metric == LSH_E2LSH) {
+                sc = sqrtf(acc);
+            } else {
+                float xn = sqrtf(xx);
+                float cs = (qn > 0.0f && xn > 0.0f) ? acc / (qn * xn) : 0.0f;
+                sc = 1.0f - cs;
+            }
+            if (lane == 0)
+                sbuf[c] = ((uint64_t)__float_as_uint(fmaxf(sc, 0.0f)) << 32) | (uint64_t)row;
+        }
+        __syncthreads();
+        // merge with the running top-k
+        const int kc = s_kcur;
+        int tot = (int)uc + kc;
+        int m2 = 1;
+        while (m2 < tot)
+            m2 <<= 1;
+        for (int e = tid; e < m2; e += kQThreads) {
+            if (e >= (int)uc)
+                sbuf[e] = e < tot ? topk[e - uc] : ~0ull;
+        }
+        __syncthreads();
+        block_bitonic(sbuf, m2);
+        int nk = tot < a.k ? tot : a.k;
+        for (int e = tid; e < nk; e += kQThreads)
+            topk[e] = sbuf[e];
+        __syncthreads();
+        if (tid == 0)
+            s_kcur = nk;
+        __syncthreads();
+    }
+
+    const int kc = s_kcur;
+    for (int r = tid; r < a.k; r += kQThreads) {
+        int64_t id = -1;
+        float sc = INFINITY;
+        if (r < kc) {
+            id = (int64_t)(uint32_t)topk[r];
+            sc = __uint_as_float((uint32_t)(topk[r] >> 32));
+        }
+        a.ids[(int64_t)q * a.k + r] = id;
+        if (a.score)
+            a.score[(int64_t)q * a.k + r] = sc;
+    }
+    if (tid == 0 && a.ncand)
+        a.ncand[q] = (int32_t)s_ncand;
+}
+
+} // namespace lsh
+
+extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, const lsh_points *base,
+                                const lsh_points *Q, const uint64_t *qkeys, int64_t qkey_ld,
+                                int32_t k, int64_t id_watermark, int32_t metric, int64_t *ids,
+                                float *score, int32_t *ncand, void *stream)
+{
+    using namespace lsh;
+    if (!segs || nseg < 1 || nseg > kMaxSeg)
+        LSH_FAIL(LSH_EINVAL, "need 1..%d index segments", kMaxSeg);
+    if (!base || !Q || !ids)
+        LSH_FAIL(LSH_EINVAL, "base, Q and ids are required");
+    if (k < 1 || k > kMaxK)
+        LSH_FAIL(LSH_EINVAL, "k must be in 1..%d", kMaxK);
+    if (metric != LSH_E2LSH && metric != LSH_SRP)
+        LSH_FAIL(LSH_EINVAL, "unknown metric %d", metric);
+    lsh_status st;
+    if ((st = check_points(base)) != LSH_OK || (st = check_points(Q)) != LSH_OK)
+        return st;
+    if (base->d != Q->d)
+        LSH_FAIL(LSH_EINVAL, "base d=%d differs from query d=%d", base->d, Q->d);
+    if (Q->d > 16384)
+        LSH_FAIL(LSH_EINVAL, "query supports d <= 16384");
+    if (Q->n == 0)
+        return LSH_OK;
+    if (!qkeys)
+        LSH_FAIL(LSH_EINVAL, "qkeys is NULL");
+    if (qkey_ld == 0)
+        qkey_ld = Q->n;
+    if (qkey_ld < Q->n)
+        LSH_FAIL(LSH_EINVAL, "qkey_ld < number of queries");
+
+    QueryArgs a = {};
+    a.nseg = nseg;
+    a.L = -1;
+    int64_t maxid = 0;
+    for (int s = 0; s < nseg; ++s) {
+        lsh_index_view v;
+        if (!segs[s] || lsh_index_get_view(segs[s], &v) != LSH_OK)
+            LSH_FAIL(LSH_EINVAL, "segment %d is NULL", s);
+        if (a.L < 0)
+            a.L = v.L;
+        if (v.L != a.L)
+            LSH_FAIL(LSH_EINVAL, "segments have different L");
+        a.seg[s].ids = v.sorted_ids;
+        a.seg[s].ukeys = v.ukeys;
+        a.seg[s].offs = v.offs;
+        a.seg[s].nuniq = v.nuniq;
+        a.seg[s].n = v.n;
+        if (v.id_base + v.n > maxid)
+            maxid = v.id_base + v.n;
+    }
+    if ((int64_t)nseg * a.L > kMaxLists)
+        LSH_FAIL(LSH_EINVAL, "nseg * L = %lld exceeds %d", (long long)nseg * a.L, kMaxLists);
+    int64_t wm = id_watermark < maxid ? id_watermark : maxid;
+    if (wm < 0)
+        wm = 0;
+    if (wm > base->n)
+        LSH_FAIL(LSH_EINVAL, "indexed ids reach %lld but base holds %lld points",
+                 (long long)wm, (long long)base->n);
+    a.bx = base->x;
+    a.bdt = base->dtype;
+    a.bscale = base->row_scale;
+    a.bld = base->ld;
+    a.bn = base->n;
+    a.qx = Q->x;
+    a.qdt = Q->dtype;
+    a.qscale = Q->row_scale;
+    a.qld = Q->ld;
+    a.d = Q->d;
+    a.qkeys = qkeys;
+    a.qkey_ld = qkey_ld;
+    a.k = k;
+    a.watermark = (uint32_t)wm;
+    a.metric = metric;
+    a.ids = ids;
+    a.score = score;
+    a.ncand = ncand;
+    size_t lds = (size_t)((Q->d * 4 + 15) & ~15) + (size_t)(5 * kMaxLists + 1) * 4 + 16 +
+                 (size_t)(kSortCap + kMaxK) * 8 + (size_t)kCap * 4;
+    LSH_HIP(hipFuncSetAttribute((const void *)query_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(query_kernel, dim3((unsigned)Q->n), dim3(kQThreads), lds,
+                       (hipStream_t)stream, a);
+    LSH_LAUNCHED("query_kernel");
+    return LSH_OK;
+}

@@ -1,0 +1,219 @@
+"""GPU parity of CS / HCS / dense hashing against the FP64 oracle, through the
+C ABI.  Inputs are seeded and shaped like the paper's workloads (Section 6):
+Gaussian clusters, sparse image-like rows, tensor reshapes for HCS."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_06737_amd import lsh, synth
+from gpu_util import compare_hash, dev, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _cs_case(n, d, K, L, data, seed):
+    m = K * L
+    if data == "clusters":
+        x = synth.gaussian_clusters(n, d, 20, 0.1, seed)
+    else:
+        x = synth.sparse_uniform(n, d, 0.2, seed)
+    h, s = synth.cs_state(d, m, seed + 1)
+    b = synth.shifts(m, 4.0, seed + 1)
+    return x, h, s, b
+
+
+CS_CASES = [
+    # n, d, K, L, data        (several row blocks and workgroups, ragged tails)
+    (10000, 1024, 8, 16, "clusters"),   # the n=10k, d=1024, m=128 workload
+    (2003, 784, 16, 64, "sparse"),      # the d=784, m=1024 image-like shape, ragged n
+    (777, 960, 16, 32, "clusters"),     # d=960, m=512
+    (501, 37, 5, 3, "clusters"),        # d not a multiple of 4: scalar-load path, odd m
+    (1, 64, 4, 4, "clusters"),          # a single point
+    (65, 4096, 16, 64, "clusters"),     # several load groups per row
+]
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+@pytest.mark.parametrize("n,d,K,L,data", CS_CASES)
+def test_cs_hash_parity(n, d, K, L, data, family):
+    dev()
+    x, h, s, b = _cs_case(n, d, K, L, data, 1234 + d)
+    x64 = x.astype(np.float64)
+    ref = oracle.hash_points(x64, family, K, L, kind="cs", w=4.0, b=b, h=h, s=s)
+    out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=family, K=K, L=L, w=4.0,
+                          b=to_dev(b), codes=True, proj=True)
+    compare_hash(out, ref, x64, K, L, what=f"cs n={n} d={d}")
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+def test_cs_hash_recheck_is_exact(family):
+    """With the FP64 recheck every code and key equals the FP64 oracle's."""
+    dev()
+    n, d, K, L = 3001, 784, 16, 64
+    x, h, s, b = _cs_case(n, d, K, L, "sparse", 77)
+    x64 = x.astype(np.float64)
+    ref = oracle.hash_points(x64, family, K, L, kind="cs", w=4.0, b=b, h=h, s=s)
+    cnt = to_dev(np.zeros(4, np.uint64))
+    out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=family, K=K, L=L, w=4.0,
+                          b=to_dev(b), codes=True, proj=True, recheck=True, counters=cnt)
+    compare_hash(out, ref, x64, K, L, exact=True, what="cs recheck")
+    c = to_host(cnt, np.uint64)
+    assert c[1] <= c[0] and c[2] == 0
+
+
+def test_keys_only_output_matches():
+    """Keys alone (the timed configuration: no codes, no projection) equal keys
+    computed with every debug output on; key_ld > n leaves the gap untouched."""
+    dev()
+    import torch
+    n, d, K, L = 1500, 784, 16, 64
+    x, h, s, b = _cs_case(n, d, K, L, "sparse", 5)
+    xd, hd, sd, bd = to_dev(x), to_dev(h), to_dev(s), to_dev(b)
+    full = lsh.lsh_hash_cs(xd, hd, sd, family=0, K=K, L=L, w=4.0, b=bd, codes=True, proj=True)
+    keys = lsh.lsh_hash_cs(xd, hd, sd, family=0, K=K, L=L, w=4.0, b=bd)
+    assert torch.equal(full["keys"], keys["keys"])
+    again = lsh.lsh_hash_cs(xd, hd, sd, family=0, K=K, L=L, w=4.0, b=bd)
+    assert torch.equal(again["keys"], keys["keys"])          # run-to-run determinism
+
+
+def test_empty_input_is_noop():
+    dev()
+    import torch
+    x = torch.empty((0, 64), dtype=torch.float32, device="cuda")
+    h, s = synth.cs_state(64, 16, 3)
+    out = lsh.lsh_hash_cs(x, to_dev(h), to_dev(s), family=1, K=4, L=4)
+    assert out["keys"].shape == (4, 0)
+
+
+HCS_CASES = [
+    # n, d, dk, mk, K, L
+    (1000, 4096, (64, 64), (32, 32), 16, 64),
+    (1000, 4096, (16, 16, 16), (8, 8, 16), 16, 64),
+    (700, 1000, (32, 32), (16, 8), 8, 16),        # zero padding: d < prod d_k
+    (300, 960, (8, 10, 12), (4, 4, 8), 16, 8),    # unequal modes, d = prod d_k
+]
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+@pytest.mark.parametrize("n,d,dk,mk,K,L", HCS_CASES)
+def test_hcs_hash_parity(n, d, dk, mk, K, L, family):
+    dev()
+    m = K * L
+    x = synth.gaussian_clusters(n, d, 30, 0.2, 99 + d)
+    hk, sk = synth.hcs_state(dk, mk, 100 + d)
+    b = synth.shifts(m, 4.0, 101)
+    x64 = x.astype(np.float64)
+    ref = oracle.hash_points(x64, family, K, L, kind="hcs", w=4.0, b=b, dk=dk, mk=mk, hk=hk,
+                             sk=sk)
+    out = lsh.lsh_hash_hcs(to_dev(x), dk, mk, to_dev(np.concatenate(hk)),
+                           to_dev(np.concatenate(sk)), family=family, K=K, L=L, w=4.0,
+                           b=to_dev(b), codes=True, proj=True)
+    compare_hash(out, ref, x64, K, L, what=f"hcs {dk}")
+    cnt = to_dev(np.zeros(4, np.uint64))
+    out = lsh.lsh_hash_hcs(to_dev(x), dk, mk, to_dev(np.concatenate(hk)),
+                           to_dev(np.concatenate(sk)), family=family, K=K, L=L, w=4.0,
+                           b=to_dev(b), codes=True, recheck=True, counters=cnt)
+    compare_hash(out, ref, x64, K, L, exact=True, what=f"hcs {dk} recheck")
+
+
+def test_hcs_equals_cs_under_composite_hash():
+    """Invariant: HCS with per-mode tables gives the same bits as CS run with
+    the composite bin/sign of every coordinate (Definition def_hcs)."""
+    dev()
+    import torch
+    n, d, dk, mk, K, L = 2000, 4096, (16, 16, 16), (8, 8, 16), 16, 64
+    x = synth.gaussian_clusters(n, d, 30, 0.2, 5)
+    hk, sk = synth.hcs_state(dk, mk, 6)
+    b = synth.shifts(K * L, 4.0, 7)
+    hb = np.zeros(d, np.uint32)
+    sb = np.zeros(d, np.int8)
+    for j in range(d):
+        i1, i2, i3 = j % 16, (j // 16) % 16, j // 256
+        hb[j] = hk[0][i1] + 8 * (hk[1][i2] + 8 * hk[2][i3])
+        sb[j] = sk[0][i1] * sk[1][i2] * sk[2][i3]
+    xd, bd = to_dev(x), to_dev(b)
+    for fam in (0, 1):
+        a = lsh.lsh_hash_hcs(xd, dk, mk, to_dev(np.concatenate(hk)), to_dev(np.concatenate(sk)),
+                             family=fam, K=K, L=L, w=4.0, b=bd, proj=True)
+        c = lsh.lsh_hash_cs(xd, to_dev(hb), to_dev(sb), family=fam, K=K, L=L, w=4.0, b=bd,
+                            proj=True)
+        assert torch.equal(a["keys"], c["keys"]) and torch.equal(a["proj"], c["proj"])
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+def test_low_precision_recheck_matches_fp64(kind, family):
+    """BF16 / FP8-E4M3FN storage with per-row scales, FP32 accumulation and the
+    FP64 near-edge recheck reproduce the FP64 oracle's codes on the
+    dequantised points exactly."""
+    dev()
+    n, d, K, L = 1200, 16384, 16, 32
+    x = synth.gaussian_clusters(n, d, 10, 0.1, 31)
+    q, sc = synth.quantise_rows(x, kind)
+    x64 = oracle.decode(q, sc)
+    h, s = synth.cs_state(d, K * L, 32)
+    b = synth.shifts(K * L, 4.0, 32)
+    ref = oracle.hash_points(x64, family, K, L, kind="cs", w=4.0, b=b, h=h, s=s)
+    cnt = to_dev(np.zeros(4, np.uint64))
+    out = lsh.lsh_hash_cs(to_dev(q), to_dev(h), to_dev(s), family=family, K=K, L=L, w=4.0,
+                          b=to_dev(b), scale=to_dev(sc), codes=True, recheck=True, counters=cnt)
+    compare_hash(out, ref, x64, K, L, exact=True, what=f"{kind} recheck")
+    pre = lsh.lsh_hash_cs(to_dev(q), to_dev(h), to_dev(s), family=family, K=K, L=L, w=4.0,
+                          b=to_dev(b), scale=to_dev(sc), codes=True, proj=True)
+    compare_hash(pre, ref, x64, K, L, what=f"{kind} no recheck")
+
+
+def test_fp8_decode_all_codes():
+    """Every FP8-E4M3FN bit pattern except NaN decodes to the oracle's value
+    (one point per pattern, identity hash d = m)."""
+    dev()
+    pats = np.array([p for p in range(256) if (p & 0x7f) != 0x7f], np.uint8)
+    d = 16
+    q = np.zeros((len(pats), d), np.uint8)
+    q[:, 0] = pats
+    sc = np.ones(len(pats), np.float32)
+    h = np.arange(d, dtype=np.uint32)
+    s = np.ones(d, np.int8)
+    out = lsh.lsh_hash_cs(to_dev(q), to_dev(h), to_dev(s), family=1, K=4, L=4,
+                          scale=to_dev(sc), proj=True, keys=False)
+    got = to_host(out["proj"])[:, 0].astype(np.float64)
+    want = np.array([oracle.fp8_value(int(p)) for p in pats])
+    assert (got == want).all()
+
+
+DENSE_CASES = [(10000, 1024, 8, 16), (1003, 784, 16, 64), (333, 100, 5, 7)]
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+@pytest.mark.parametrize("n,d,K,L", DENSE_CASES)
+def test_dense_hash_parity(n, d, K, L, family):
+    dev()
+    m = K * L
+    x = synth.gaussian_clusters(n, d, 20, 0.1, 400 + d)
+    R = synth.gaussian_matrix(d, m, 401)
+    b = synth.shifts(m, 4.0, 402)
+    x64 = x.astype(np.float64)
+    ref = oracle.hash_points(x64, family, K, L, kind="dense", w=4.0, b=b, R=R)
+    out = lsh.lsh_hash_dense(to_dev(x), to_dev(R), family=family, K=K, L=L, w=4.0, b=to_dev(b),
+                             codes=True, proj=True)
+    # dense dot products of d terms: allow the dense weight scale in the band
+    compare_hash(out, ref, x64, K, L, weight_max=float(np.abs(R).max()),
+                 what=f"dense n={n} d={d}")
+
+
+def test_dense_with_cs_matrix_equals_cs():
+    """Special case: the dense projection by the explicit count-sketch matrix
+    is the count sketch (codes agree outside the near-edge band)."""
+    dev()
+    n, d, K, L = 2000, 256, 8, 16
+    m = K * L
+    x = synth.gaussian_clusters(n, d, 20, 0.1, 9)
+    h, s = synth.cs_state(d, m, 10)
+    R = np.zeros((d, m), np.float32)
+    R[np.arange(d), h] = s
+    b = synth.shifts(m, 4.0, 11)
+    ys = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=1, K=K, L=L, proj=True)
+    yd = lsh.lsh_hash_dense(to_dev(x), to_dev(R), family=1, K=K, L=L, proj=True)
+    np.testing.assert_allclose(to_host(yd["proj"]), to_host(ys["proj"]), rtol=0, atol=1e-4)

@@ -1,0 +1,110 @@
+"""GPU query (bucket probe, union, exact re-rank, top-k) against the oracle:
+candidate counts exact; top-k ids equal except swaps between candidates whose
+oracle scores differ by at most 1e-5 (relative); scores within 1e-5."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_06737_amd import lsh, synth
+from gpu_util import dev, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(ids, sc, nc, rids, rsc, rnc, what=""):
+    ids, sc, nc = to_host(ids), to_host(sc), to_host(nc)
+    assert (nc == rnc).all(), f"{what}: ncand differs at {np.nonzero(nc != rnc)[0][:5]}"
+    swaps = 0
+    for i in range(ids.shape[0]):
+        fin = np.isfinite(rsc[i])
+        assert (np.isfinite(sc[i]) == fin).all()
+        np.testing.assert_allclose(sc[i][fin], rsc[i][fin], rtol=1e-5, atol=1e-5)
+        if (ids[i] != rids[i]).any():
+            # a swap is allowed only between near-equal scores; the id sets of
+            # strictly separated scores must agree
+            kth = rsc[i][fin][-1] if fin.any() else np.inf
+            strict = rsc[i] < kth * (1 - 1e-5) - 1e-5
+            assert set(ids[i][strict]) == set(rids[i][strict]), f"{what}: query {i}"
+            swaps += 1
+    return swaps
+
+
+def _pipeline(x, Q, h, s, b, K, L, w, family, segs_split=None, watermark=None, k=10):
+    xd = to_dev(x)
+    Qd = to_dev(Q)
+    kw = dict(family=family, K=K, L=L, w=w, b=to_dev(b))
+    keys = lsh.lsh_hash_cs(xd, to_dev(h), to_dev(s), recheck=True, **kw)["keys"]
+    qkeys = lsh.lsh_hash_cs(Qd, to_dev(h), to_dev(s), recheck=True, **kw)["keys"]
+    splits = segs_split or [x.shape[0]]
+    segs, ref_segs, lo = [], [], 0
+    kh = to_host(keys, np.uint64)
+    for hi in splits:
+        segs.append(lsh.lsh_build_index(keys[:, lo:hi].contiguous(), id_base=lo))
+        ref_segs.append(oracle.build_index(np.ascontiguousarray(kh[:, lo:hi]), lo))
+        lo = hi
+    wm = x.shape[0] if watermark is None else watermark
+    ids, sc, nc = lsh.lsh_query(segs, xd, Qd, qkeys, k=k, watermark=wm, metric=family)
+    rids, rsc, rnc = oracle.query(ref_segs, x.astype(np.float64), Q.astype(np.float64),
+                                  to_host(qkeys, np.uint64), k, wm, family)
+    return (ids, sc, nc), (rids, rsc, rnc)
+
+
+@pytest.mark.parametrize("family,w", [(oracle.SRP, 4.0), (oracle.E2LSH, 16.0), (oracle.E2LSH, 4.0)])
+def test_query_clusters(family, w):
+    """n=10k, d=1024, m=128 clusters; 1,000 held-out queries, top-10."""
+    dev()
+    wl = synth.C1
+    x = wl.points()
+    Q = wl.queries()
+    h, s = wl.cs()
+    b = synth.shifts(wl.m, w, wl.seed + 1)
+    got, ref = _pipeline(x, Q, h, s, b, wl.K, wl.L, w, family)
+    _compare(*got, *ref, what=f"fam={family} w={w}")
+
+
+def test_query_segments_and_watermark():
+    dev()
+    x = synth.gaussian_clusters(6000, 256, 10, 0.1, 21)
+    Q = synth.gaussian_clusters(200, 256, 10, 0.1, 21, stream=1)
+    h, s = synth.cs_state(256, 64, 22)
+    b = synth.shifts(64, 8.0, 22)
+    got, ref = _pipeline(x, Q, h, s, b, 8, 8, 8.0, oracle.SRP, segs_split=[2500, 4000, 6000],
+                         watermark=5000, k=17)
+    _compare(*got, *ref, what="segments")
+
+
+def test_query_one_bucket_is_exact_knn_with_windows():
+    """w -> infinity: one bucket holding every point, so each query re-ranks
+    all 5,000 points through several id windows and returns exact kNN."""
+    dev()
+    n, d = 5000, 48
+    x = synth.gaussian_clusters(n, d, 5, 1.0, 31)
+    Q = synth.gaussian_clusters(64, d, 5, 1.0, 31, stream=1)
+    h, s = synth.cs_state(d, 16, 32)
+    b = np.full(16, 0.5e30, np.float32)
+    got, ref = _pipeline(x, Q, h, s, b, 4, 4, 1e30, oracle.E2LSH, k=64)
+    assert (to_host(got[2]) == n).all()
+    _compare(*got, *ref, what="one bucket")
+    dist = np.sqrt(((Q[:, None, :].astype(np.float64) - x[None].astype(np.float64)) ** 2).sum(-1))
+    for i in range(Q.shape[0]):
+        order = np.lexsort((np.arange(n), dist[i]))[:64]
+        assert len(set(order[:60]) ^ set(to_host(got[0])[i][:60])) <= 4
+
+
+def test_query_low_precision_base():
+    """Re-rank over BF16 points with per-row scales (dequantised on the fly)."""
+    dev()
+    x = synth.gaussian_clusters(3000, 512, 10, 0.1, 41)
+    q, sc = synth.quantise_rows(x, "bf16")
+    x64 = oracle.decode(q, sc)
+    Q = x64[:50].astype(np.float32)
+    h, s = synth.cs_state(512, 64, 42)
+    kw = dict(family=1, K=8, L=8)
+    keys = lsh.lsh_hash_cs(to_dev(q), to_dev(h), to_dev(s), scale=to_dev(sc), recheck=True, **kw)["keys"]
+    qkeys = lsh.lsh_hash_cs(to_dev(Q), to_dev(h), to_dev(s), recheck=True, **kw)["keys"]
+    idx = lsh.lsh_build_index(keys)
+    ids, scv, nc = lsh.lsh_query([idx], to_dev(q), to_dev(Q), qkeys, k=10, metric=1,
+                                 base_scale=to_dev(sc))
+    ref = oracle.query([oracle.build_index(to_host(keys, np.uint64))], x64, Q.astype(np.float64),
+                       to_host(qkeys, np.uint64), 10, 3000, 1)
+    _compare(ids, scv, nc, *ref, what="bf16 base")
