@@ -1,27 +1,37 @@
 // Count-sketch and higher-order count-sketch LSH hashing on gfx950.
 //
-// One fused, HBM-bound kernel per call: stream the rows of X once, scatter
-// every coordinate into its sketch bin (count sketch, Section 3.2 Eq. eq_cs;
-// the higher-order count sketch of Eq. eqhcs is the same scatter under the
-// composite bin of the per-mode hashes), discretise the m bins
+// One fused, HBM-bound kernel per call: stream the rows of X once, add every
+// coordinate into its sketch bin with its sign (count sketch, Section 3.2 Eq.
+// eq_cs; the higher-order count sketch of Eq. eqhcs is the same sum under the
+// composite bin and sign of the per-mode hashes), discretise the m bins
 // (floor((sqrt(m) y + b)/w), Definitions CS_Eucl_LSH / HCS_Eucl_LSH, or
-// sgn(y), Definitions cs_consine_lsh / hcs_consine_lsh), and fold each table's
-// K codes into its 64-bit bucket key (Section 3.1).
+// sgn(y), Definitions cs_consine_lsh / hcs_consine_lsh), and fold each
+// table's K codes into its 64-bit bucket key (Section 3.1).
 //
 // Work decomposition:
 //   * a workgroup of W waves shares the packed hash table (one 16-bit entry
-//     per coordinate: bin << 1 | sign) in LDS, built once per workgroup from
-//     h/s (CS) or from the per-mode tables (HCS);
-//   * each wave owns blocks of RB consecutive rows and keeps m FP32 bins of
-//     its own in LDS; a row is streamed in 16-byte chunks, chunk c of the row
-//     always goes to lane c mod 64, and the next chunk group is loaded before
-//     the current one is scattered (two register buffers);
-//   * after a row, the wave discretises its bins (E2LSH: one lane per table;
-//     SRP: one lane per component plus ballots), and stages the L keys of
-//     its RB rows in LDS so the key stores leave as 8-key (64-byte) runs.
-// The optional FP64 recheck recomputes, in ascending coordinate order, any
-// component whose FP32 value lies within the rounding-error bound
-// gamma_{c-1} * sum|terms| of a bin edge (or of zero for SRP).
+//     per coordinate: LDS slot of its bin << 1 | sign), built once per
+//     workgroup from h/s (CS) or from the per-mode tables (HCS), together
+//     with the largest bin population c_max;
+//   * each wave hashes blocks of RB consecutive rows.  A whole row is loaded
+//     into registers with 16-byte loads (chunk c of the row in lane c mod 64)
+//     -- two rows at a time when they are short, so the second row's loads
+//     are in flight while the first is summed;
+//   * fixed-point sums: LDS float atomics are slow on this GPU, integer ones
+//     run at streaming speed.  Each row gets an exponent k from its largest
+//     magnitude 2^e and c_max (k = 31 - ceil(log2(c_max + 1)) - e), every
+//     term s_j x_j is scaled by 2^k, truncated to int32 and added with an LDS
+//     integer atomic into the wave's bins.  No bin can overflow, the sum is
+//     exact and independent of the order of the atomics (so results are
+//     bit-reproducible), and y = sum * 2^-k differs from the real sum by less
+//     than c * 2^-k for a bin of c terms;
+//   * after a row, the wave discretises its bins (E2LSH: one lane per table,
+//     bins padded one word per 16 so those reads are conflict-free; SRP: one
+//     lane per component plus ballots) and stages the L keys of its RB rows
+//     in LDS, so key stores leave as 8-key (64-byte) runs.
+// The optional FP64 recheck recomputes, in ascending coordinate order and in
+// FP64, every component whose value lies within the rigorous bound of its
+// error from a bin edge (E2LSH) or from zero (SRP).
 
 #include <math.h>
 #include <stdarg.h>
@@ -31,11 +41,14 @@
 
 namespace lsh {
 
-constexpr int kRowsPerBlock = 8;  // RB: rows a wave hashes before writing keys
-constexpr int kChunksPerLane = 4; // 16-byte chunks per lane per load group
+constexpr int kRowsPerBlock = 8; // RB: rows a wave hashes before writing keys
 constexpr int kMaxModes = 8;
 
 __host__ __device__ constexpr int align16(int v) { return (v + 15) & ~15; }
+
+// LDS slot of sketch bin l: one pad word after every 16 bins, so that lanes
+// reading K consecutive bins each (one lane per table) hit distinct banks.
+__host__ __device__ constexpr int bin_pos(int l) { return l + (l >> 4); }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -46,7 +59,7 @@ struct HashArgs {
     int32_t d;
     const float *row_scale;
     int32_t m, K, L;
-    float alpha32;  // sqrt(m) (1 for dense-style scaling, unused here)
+    float alpha32;  // sqrt(m)
     float inv_w32;
     float w32;
     int32_t w_pow2; // 1 when w is a power of two, so /w == *(1/w) exactly
@@ -68,16 +81,16 @@ struct HashArgs {
     // recheck support (workspace)
     const uint32_t *csr_off;
     const uint32_t *csr_idx;
-    const uint32_t *cmax;
     // layout
-    int32_t waves;       // waves per workgroup
-    int32_t tab_bytes;   // LDS bytes of the hash table (aligned)
-    int32_t mpad;        // bins per wave, padded to a multiple of 256
-    int32_t wave_bytes;  // LDS bytes per wave
+    int32_t waves;      // waves per workgroup
+    int32_t tab_bytes;  // LDS bytes of the hash table (aligned)
+    int32_t mpad;       // bin slots per wave, multiple of 256
+    int32_t wave_bytes; // LDS bytes per wave
 };
 
-// Bin/sign entry of coordinate j: bin << 1 | (sign < 0).
-__device__ __forceinline__ uint32_t table_entry(const HashArgs &a, int32_t j, bool &bad)
+// Bin of coordinate j in the sketch and its sign (neg = sign < 0).
+__device__ __forceinline__ uint32_t table_bin(const HashArgs &a, int32_t j, bool &bad,
+                                              uint32_t &neg_out)
 {
     uint32_t bin;
     uint32_t neg;
@@ -107,7 +120,16 @@ __device__ __forceinline__ uint32_t table_entry(const HashArgs &a, int32_t j, bo
         bad = true;
         bin = 0;
     }
-    return (bin << 1) | neg;
+    neg_out = neg;
+    return bin;
+}
+
+// Packed LDS table entry of coordinate j: LDS slot of its bin << 1 | sign bit.
+__device__ __forceinline__ uint32_t table_entry(const HashArgs &a, int32_t j, bool &bad)
+{
+    uint32_t neg;
+    uint32_t bin = table_bin(a, j, bad, neg);
+    return ((uint32_t)bin_pos((int)bin) << 1) | neg;
 }
 
 // ----------------------------------------------------------------- decoding
@@ -137,28 +159,26 @@ __device__ __forceinline__ float fp8_to_f32(uint32_t byte)
     return __uint_as_float(__float_as_uint(mag) | ((byte & 0x80u) << 24));
 }
 
-// Element e of a 16-byte chunk.
-template <int DT> __device__ __forceinline__ float elem_value(u32x4 v, int e)
+// Element e of a 16-byte chunk (ALIGNED) or the single element of a chunk.
+template <int DT, bool AL> __device__ __forceinline__ float chunk_value(u32x4 v, int e)
 {
-    uint32_t word = v[e / (Elem<DT>::per16 / 4)];
-    if constexpr (DT == LSH_F32) {
-        return __uint_as_float(word);
-    } else if constexpr (DT == LSH_BF16) {
-        return __uint_as_float((e & 1) ? (word & 0xffff0000u) : (word << 16));
+    if constexpr (!AL) {
+        uint32_t u = v[0];
+        if constexpr (DT == LSH_F32)
+            return __uint_as_float(u);
+        else if constexpr (DT == LSH_BF16)
+            return __uint_as_float((u & 0xffffu) << 16);
+        else
+            return fp8_to_f32(u & 0xffu);
     } else {
-        return fp8_to_f32((word >> (8 * (e & 3))) & 0xffu);
+        uint32_t word = v[e / (Elem<DT>::per16 / 4)];
+        if constexpr (DT == LSH_F32)
+            return __uint_as_float(word);
+        else if constexpr (DT == LSH_BF16)
+            return __uint_as_float((e & 1) ? (word & 0xffff0000u) : (word << 16));
+        else
+            return fp8_to_f32((word >> (8 * (e & 3))) & 0xffu);
     }
-}
-
-// Value of one element given its bit pattern in the low bits of u.
-template <int DT> __device__ __forceinline__ float bits_value(uint32_t u)
-{
-    if constexpr (DT == LSH_F32)
-        return __uint_as_float(u);
-    else if constexpr (DT == LSH_BF16)
-        return __uint_as_float((u & 0xffffu) << 16);
-    else
-        return fp8_to_f32(u & 0xffu);
 }
 
 template <int DT> __device__ __forceinline__ float scalar_value(const void *x, int64_t idx)
@@ -172,13 +192,12 @@ template <int DT> __device__ __forceinline__ float scalar_value(const void *x, i
     }
 }
 
-// --------------------------------------------------------------- LDS layout
+// ----------------------------------------------------------- wave helpers
 
 struct WaveLds {
-    float *bins;     // [mpad]
-    float *absb;     // [mpad] (recheck only)
-    uint64_t *stage; // [L * RB]
-    uint64_t *mask;  // [ceil(m/64)] (SRP)
+    int32_t *bins;   // [mpad] fixed-point sums, indexed by bin_pos
+    uint64_t *stage; // [L * RB] keys of the current row block
+    uint64_t *mask;  // [ceil(m/64)] SRP sign bits of the current row
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -187,15 +206,35 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// ------------------------------------------------------------- the epilogue
-
-// gamma_{c-1} for FP32 recursive summation of c terms, plus slack.
-__device__ __forceinline__ double sum_gamma(uint32_t c)
+__device__ __forceinline__ float wave_max(float v)
 {
-    const double u = 0x1.0p-24;
-    double k = c > 1 ? (double)(c - 1) : 0.0;
-    return k * u / (1.0 - k * u) * (1.0 + 1e-9);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
 }
+
+// Per-row scale (1 for FP32 points), read through the scalar cache: row is
+// the same in every lane.
+template <int DT> __device__ __forceinline__ float row_scale_of(const HashArgs &a, int64_t row)
+{
+    if constexpr (DT == LSH_F32) {
+        return 1.0f;
+    } else {
+        int64_t r = ((int64_t)__builtin_amdgcn_readfirstlane((int)(row >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)row);
+        return a.row_scale[r];
+    }
+}
+
+// What the epilogue needs to turn a bin's fixed-point sum into y.
+struct RowFix {
+    float scale;  // row scale (1 for FP32)
+    float fs;     // scale * 2^-k as FP32 (may underflow for tiny rows; fast path only)
+    float af;     // fs * sqrt(m) / w (fast E2LSH path)
+    double s2k;   // scale * 2^-k in FP64 (exact)
+    double ey;    // bound on |y - y_fp64| before the per-component term (recheck)
+};
 
 // Exact FP64 value of component l of row `row`, summed in ascending
 // coordinate order exactly as an FP64 evaluation of the definition would.
@@ -213,34 +252,36 @@ __device__ double exact_component(const HashArgs &a, const uint16_t *tab, int64_
     return y;
 }
 
+// ------------------------------------------------------------- the epilogue
+
+// Code of E2LSH component l (Definition CS_Eucl_LSH): floor((sqrt(m) y + b)/w).
 template <int DT, bool RECHECK>
-__device__ __forceinline__ int32_t e2lsh_code(const HashArgs &a, const uint16_t *tab, const WaveLds &w,
-                                              const float *bl, int64_t row, float scale, double gam,
-                                              int32_t l, bool count, unsigned &nflag,
-                                              unsigned &nchg, unsigned &nsat)
+__device__ __forceinline__ int32_t e2lsh_code(const HashArgs &a, const uint16_t *tab,
+                                              const WaveLds &w, const float *bl, int64_t row,
+                                              const RowFix &rf, int32_t l, bool count,
+                                              unsigned &nflag, unsigned &nchg, unsigned &nsat)
 {
-    float y = w.bins[l];
+    const int pl = bin_pos(l);
+    const int32_t isum = w.bins[pl];
     double cd;
     if constexpr (!RECHECK) {
-        float v = fmaf(a.alpha32 * scale, y, bl[l]);
-        float c = a.w_pow2 ? floorf(v * a.inv_w32) : floorf(v / a.w32);
-        cd = (double)c;
+        // bl holds b / w here; the row factor sqrt(m) * scale * 2^-k / w is folded in
+        float v = fmaf(rf.af, (float)isum, bl[pl]);
+        cd = (double)floorf(v);
         if (a.proj && count)
-            a.proj[row * a.m + l] = y * scale;
+            a.proj[row * a.m + l] = (float)isum * rf.fs;
     } else {
-        double y64 = (double)scale * (double)y; // exact
+        double y64 = (double)isum * rf.s2k;
         double t = __dmul_rn(a.alpha64, y64);
-        double b64 = (double)bl[l];
+        double b64 = (double)bl[pl];
         double v = __dadd_rn(t, b64);
         double q = a.w_pow2 ? v * a.inv_w64 : v / a.w64;
         cd = floor(q);
-        // distance to the nearest bin edge vs the error bound of v
-        double A = (double)w.absb[l];
-        double Ey = (double)scale * (A * gam * 1.0000001 + 1e-40);
-        double Ev = a.alpha64 * Ey * (1.0 + 1e-12) + 1e-15 * (fabs(t) + fabs(v) + b64);
+        double Ey = rf.ey + fabs(y64) * 0x1.0p-51;
+        double Ev = a.alpha64 * Ey * (1.0 + 1e-12) + 0x1.0p-50 * (fabs(t) + fabs(v) + fabs(b64));
         double dist = fabs(v - a.w64 * rint(q));
         if (dist <= Ev) {
-            double ye = exact_component<DT>(a, tab, row, (double)scale, l);
+            double ye = exact_component<DT>(a, tab, row, (double)rf.scale, l);
             double ve = __dadd_rn(__dmul_rn(a.alpha64, ye), b64);
             double ce = floor(ve / a.w64);
             if (count) {
@@ -263,15 +304,14 @@ __device__ __forceinline__ int32_t e2lsh_code(const HashArgs &a, const uint16_t 
 template <int DT, bool RECHECK>
 __device__ void epilogue_e2lsh(const HashArgs &a, const uint16_t *tab, const WaveLds &w,
                                const float *bl, const uint64_t *hinit, int64_t row, int rr,
-                               double gam, unsigned &nflag, unsigned &nchg, unsigned &nsat)
+                               const RowFix &rf, unsigned &nflag, unsigned &nchg, unsigned &nsat)
 {
     const int lane = lane_id();
-    const float scale = a.row_scale ? a.row_scale[row] : 1.0f;
     for (int t = lane; t < a.L; t += kWave) {
         const int32_t l0 = t * a.K;
         uint64_t key = e2lsh_key(a.K, hinit[2 * t], hinit[2 * t + 1], [&](int r, bool first) {
-            int32_t c = e2lsh_code<DT, RECHECK>(a, tab, w, bl, row, scale, gam, l0 + r, first,
-                                                nflag, nchg, nsat);
+            int32_t c = e2lsh_code<DT, RECHECK>(a, tab, w, bl, row, rf, l0 + r, first, nflag,
+                                                nchg, nsat);
             if (first && a.codes)
                 a.codes[row * a.m + l0 + r] = c;
             return c;
@@ -280,35 +320,38 @@ __device__ void epilogue_e2lsh(const HashArgs &a, const uint16_t *tab, const Wav
     }
 }
 
+// SRP family: bit = [y > 0] (Definition cs_consine_lsh).  The fixed-point sum
+// has the sign of y except within its error bound of 0 (rechecked on request).
 template <int DT, bool RECHECK>
 __device__ void epilogue_srp(const HashArgs &a, const uint16_t *tab, const WaveLds &w, int64_t row,
-                             int rr, double gam, unsigned &nflag, unsigned &nchg)
+                             int rr, const RowFix &rf, unsigned &nflag, unsigned &nchg)
 {
     const int lane = lane_id();
-    const float scale = a.row_scale ? a.row_scale[row] : 1.0f;
     const int ngroups = (a.m + kWave - 1) / kWave;
     for (int g = 0; g < ngroups; ++g) {
         int32_t l = g * kWave + lane;
         bool bit = false;
         if (l < a.m) {
-            float y = w.bins[l];
-            bit = y > 0.0f;
-            double y64 = (double)scale * (double)y;
+            const int32_t isum = w.bins[bin_pos(l)];
+            bit = isum > 0;
+            float yout = (float)isum * rf.fs;
             if constexpr (RECHECK) {
-                double Ey = (double)scale * ((double)w.absb[l] * gam * 1.0000001 + 1e-40);
+                double y64 = (double)isum * rf.s2k;
+                double Ey = rf.ey + fabs(y64) * 0x1.0p-51;
                 if (fabs(y64) <= Ey) {
-                    double ye = exact_component<DT>(a, tab, row, (double)scale, l);
+                    double ye = exact_component<DT>(a, tab, row, (double)rf.scale, l);
                     bool be = ye > 0.0;
                     ++nflag;
                     nchg += be != bit;
                     bit = be;
                     y64 = ye;
                 }
+                yout = (float)y64;
             }
             if (a.codes)
                 a.codes[row * a.m + l] = bit ? 1 : 0;
             if (a.proj)
-                a.proj[row * a.m + l] = RECHECK ? (float)y64 : y * scale;
+                a.proj[row * a.m + l] = yout;
         }
         uint64_t bal = __ballot(bit);
         if (lane == 0)
@@ -328,170 +371,203 @@ __device__ void epilogue_srp(const HashArgs &a, const uint16_t *tab, const WaveL
 
 // ------------------------------------------------------------------ kernel
 
-template <int FAM, int DT, bool ALIGNED, bool RECHECK>
+// CH: 16-byte chunks (ALIGNED) or single elements per lane per row; a row
+// has at most 64 * CH of them.
+template <int FAM, int DT, bool ALIGNED, bool RECHECK, int CH>
 __global__ __launch_bounds__(512) void hash_kernel(HashArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     uint16_t *tab = (uint16_t *)lds;
     float *bl = (float *)(lds + a.tab_bytes);
-    uint64_t *hinit = (uint64_t *)(lds + a.tab_bytes + align16(a.m * 4));
-    unsigned char *wave_base = lds + a.tab_bytes + align16(a.m * 4) + align16(a.L * 16);
+    uint64_t *hinit = (uint64_t *)(lds + a.tab_bytes + align16(bin_pos(a.m) * 4));
+    unsigned char *wave_base = lds + a.tab_bytes + align16(bin_pos(a.m) * 4) + align16(a.L * 16);
+    __shared__ uint32_t s_cmax;
 
     const int tid = threadIdx.x;
-    const int wid = tid / kWave;
+    // wave index, made visibly uniform so the row cursor lives in SGPRs
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int lane = lane_id();
 
-    // ---- prologue: hash table, shifts, per-table digest seeds, zero bins
-    bool bad = false;
-    for (int32_t j = tid; j < a.d; j += blockDim.x)
-        tab[j] = (uint16_t)table_entry(a, j, bad);
-    if (FAM == LSH_E2LSH) {
-        for (int32_t l = tid; l < a.m; l += blockDim.x)
-            bl[l] = a.b[l];
-        for (int32_t t = tid; t < 2 * a.L; t += blockDim.x)
-            hinit[t] = mix64((uint64_t)t); // = F(2*table + wide)
-    }
     WaveLds w;
     unsigned char *mine = wave_base + (size_t)wid * a.wave_bytes;
-    w.bins = (float *)mine;
-    w.absb = (float *)(mine + a.mpad * 4);
-    w.stage = (uint64_t *)(mine + (RECHECK ? 2 : 1) * a.mpad * 4);
+    w.bins = (int32_t *)mine;
+    w.stage = (uint64_t *)(mine + a.mpad * 4);
     w.mask = w.stage + a.L * kRowsPerBlock;
-    for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4) {
-        *(float4 *)(w.bins + l) = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (RECHECK)
-            *(float4 *)(w.absb + l) = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    // ---- prologue: zero every wave's bins; wave 0's bins first count the
+    // bin populations (integer LDS atomics) to find c_max
+    if (tid == 0)
+        s_cmax = 0;
+    for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4)
+        *(int4 *)(w.bins + l) = make_int4(0, 0, 0, 0);
+    __syncthreads();
+    int32_t *cnt = (int32_t *)wave_base;
+    bool bad = false;
+    for (int32_t j = tid; j < a.d; j += blockDim.x) {
+        uint32_t ent = table_entry(a, j, bad);
+        tab[j] = (uint16_t)ent;
+        atomicAdd(&cnt[ent >> 1], 1);
     }
-    if (bad && a.counters)
+    if (FAM == LSH_E2LSH) {
+        // fast path: b / w (the row factor folds 1/w in); recheck: b as given
+        for (int32_t l = tid; l < a.m; l += blockDim.x)
+            bl[bin_pos(l)] = RECHECK ? a.b[l] : a.b[l] * a.inv_w32;
+        for (int32_t t = tid; t < 2 * a.L; t += blockDim.x)
+            hinit[t] = mix64((uint64_t)t); // = F(2 * table + wide)
+    }
+    __syncthreads();
+    for (int32_t l = tid; l < a.m; l += blockDim.x)
+        atomicMax(&s_cmax, (uint32_t)cnt[bin_pos(l)]);
+    __syncthreads();
+    for (int32_t l = tid; l < a.mpad; l += blockDim.x)
+        cnt[l] = 0;
+    if (bad && a.counters && tid == 0)
         atomicAdd(&a.counters[3], 1ull);
     __syncthreads();
 
-    double gam = 0.0;
-    if constexpr (RECHECK)
-        gam = sum_gamma(*a.cmax);
+    const uint32_t cmax = s_cmax;
+    // terms are kept below 2^(31 - hr) with c_max < 2^hr: no bin overflows int32
+    const int hr = cmax ? 32 - __clz(cmax) : 0;
+    const int koff = 31 - hr;
 
-    // ---- row blocks owned by this wave
+    // ---- rows owned by this wave
     constexpr int VEC = ALIGNED ? Elem<DT>::per16 : 1;
     const int64_t nblk = (a.n + kRowsPerBlock - 1) / kRowsPerBlock;
     const int64_t wave_gid = (int64_t)blockIdx.x * a.waves + wid;
     const int64_t wave_stride = (int64_t)gridDim.x * a.waves;
-    const int32_t nchunk = a.d / VEC;                      // d % VEC == 0 when ALIGNED
-    const int32_t group = kWave * kChunksPerLane;          // chunks per load group
-    const int32_t ngroups = (nchunk + group - 1) / group;  // load groups per row
+    const int32_t nchunk = a.d / VEC; // d % VEC == 0 when ALIGNED
 
     unsigned nflag = 0, nchg = 0, nsat = 0;
 
-    // cursor over (block, row in block, group)
-    int64_t blk = wave_gid;
-    if (blk >= nblk)
-        return;
-    auto rows_in = [&](int64_t bk) -> int {
-        int64_t r = a.n - bk * kRowsPerBlock;
-        return r < kRowsPerBlock ? (int)r : kRowsPerBlock;
-    };
-
     using T = typename Elem<DT>::T;
-    u32x4 bufA[kChunksPerLane], bufB[kChunksPerLane];
+    using Buf = u32x4[CH];
 
-    auto load = [&](u32x4 *buf, int64_t row, int32_t g) {
+    // Every lane issues exactly CH loads per row (chunks past the row end
+    // re-read chunk 0 and are not summed), so the number of loads in flight
+    // is static and each wait covers only the row being summed.
+    auto load_row = [&](Buf &buf, int64_t row) {
         const T *xr = (const T *)a.x + row * a.ld;
 #pragma unroll
-        for (int i = 0; i < kChunksPerLane; ++i) {
-            int32_t c = g * group + i * kWave + lane;
-            if (c < nchunk) {
-                if constexpr (ALIGNED) {
-                    buf[i] = __builtin_nontemporal_load((const u32x4 *)(xr + (int64_t)c * VEC));
+        for (int i = 0; i < CH; ++i) {
+            int32_t ch = i * kWave + lane;
+            ch = ch < nchunk ? ch : 0;
+            if constexpr (ALIGNED) {
+                buf[i] = __builtin_nontemporal_load((const u32x4 *)(xr + (int64_t)ch * VEC));
+            } else {
+                uint32_t u;
+                if constexpr (DT == LSH_F32)
+                    u = __float_as_uint(xr[ch]);
+                else
+                    u = (uint32_t)xr[ch];
+                buf[i] = u32x4{u, 0u, 0u, 0u};
+            }
+        }
+    };
+
+    constexpr int TW = VEC >= 2 ? VEC / 2 : 1; // table dwords per chunk
+    auto process_row = [&](const Buf &buf, int64_t row, int rr, int nrows, int64_t row0) {
+        // 1. the row's largest magnitude -> exponent e (|x| < 2^e) -> k
+        float mx = 0.0f;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            if (i * kWave + lane < nchunk) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    mx = fmaxf(mx, fabsf(chunk_value<DT, ALIGNED>(buf[i], e)));
+            }
+        }
+        const uint32_t mb = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_int(wave_max(mx)));
+        const int be = (int)((mb >> 23) & 0xffu);
+        const int e = be == 0 ? -126 : be - 126;
+        const int k = koff - e;
+
+        // 2. signed fixed-point sums into this wave's bins
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int32_t ch = i * kWave + lane;
+            if (ch < nchunk) {
+                uint32_t tw[TW];
+                if constexpr (VEC == 1) {
+                    tw[0] = tab[ch];
+                } else if constexpr (VEC == 4) {
+                    uint2 v = *(const uint2 *)(tab + ch * VEC);
+                    tw[0] = v.x;
+                    tw[1] = v.y;
                 } else {
-                    uint32_t u;
-                    if constexpr (DT == LSH_F32)
-                        u = __float_as_uint(xr[c]);
-                    else
-                        u = (uint32_t)xr[c];
-                    buf[i] = u32x4{u, 0u, 0u, 0u};
+#pragma unroll
+                    for (int q = 0; q < TW / 4; ++q) {
+                        u32x4 v = *(const u32x4 *)(tab + ch * VEC + q * 8);
+                        tw[4 * q + 0] = v[0];
+                        tw[4 * q + 1] = v[1];
+                        tw[4 * q + 2] = v[2];
+                        tw[4 * q + 3] = v[3];
+                    }
                 }
-            }
-        }
-    };
-
-    auto scatter = [&](const u32x4 *buf, int32_t g) {
 #pragma unroll
-        for (int i = 0; i < kChunksPerLane; ++i) {
-            int32_t c = g * group + i * kWave + lane;
-            if (c < nchunk) {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    uint32_t ent = tab[c * VEC + e];
-                    float v;
-                    if constexpr (ALIGNED)
-                        v = elem_value<DT>(buf[i], e);
-                    else
-                        v = bits_value<DT>(buf[i][0]);
+                for (int e2 = 0; e2 < VEC; ++e2) {
+                    uint32_t ent = VEC == 1 ? tw[0] : (tw[e2 >> 1] >> (16 * (e2 & 1))) & 0xffffu;
+                    float v = chunk_value<DT, ALIGNED>(buf[i], e2);
                     float sv = __uint_as_float(__float_as_uint(v) ^ ((ent & 1u) << 31));
-                    atomicAdd(&w.bins[ent >> 1], sv);
-                    if constexpr (RECHECK)
-                        atomicAdd(&w.absb[ent >> 1], fabsf(v));
+                    atomicAdd(&w.bins[ent >> 1], (int32_t)ldexpf(sv, k));
                 }
             }
         }
+
+        // 3. discretise, key, stage
+        wave_sync();
+        RowFix rf;
+        rf.scale = row_scale_of<DT>(a, row);
+        rf.s2k = ldexp((double)rf.scale, -k);
+        rf.fs = (float)rf.s2k;
+        rf.af = rf.fs * a.alpha32 * a.inv_w32;
+        if constexpr (RECHECK) {
+            // truncation: each term off by < 2^-k (times the scale), a bin has
+            // <= c_max terms; plus the FP64 reference's own rounding
+            // (c_max^2 * 2^(e-52) bounds gamma_{c-1} * sum|terms|)
+            rf.ey = (double)rf.scale * (double)cmax *
+                    (ldexp(1.0, -k) + (double)cmax * ldexp(1.0, e - 51));
+        } else {
+            rf.ey = 0.0;
+        }
+        if constexpr (FAM == LSH_E2LSH)
+            epilogue_e2lsh<DT, RECHECK>(a, tab, w, bl, hinit, row, rr, rf, nflag, nchg, nsat);
+        else
+            epilogue_srp<DT, RECHECK>(a, tab, w, row, rr, rf, nflag, nchg);
+        wave_sync();
+        for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4)
+            *(int4 *)(w.bins + l) = make_int4(0, 0, 0, 0);
+        if (rr == nrows - 1 && a.keys) {
+            // block complete: write the staged keys, up to 8 consecutive rows per table
+            for (int ee = lane; ee < a.L * kRowsPerBlock; ee += kWave) {
+                int t = ee / kRowsPerBlock, r = ee % kRowsPerBlock;
+                if (r < nrows)
+                    a.keys[(int64_t)t * a.key_ld + row0 + r] = w.stage[ee];
+            }
+        }
+        wave_sync();
     };
 
-    int rr = 0;                    // row within block
-    int32_t g = 0;                 // load group within row
-    int nrows = rows_in(blk);
-    load(bufA, blk * kRowsPerBlock, 0);
-    bool useA = true;
-    while (true) {
-        // next cursor position
-        int64_t nblk_i = blk;
-        int nrr = rr;
-        int32_t ng = g + 1;
-        if (ng == ngroups) {
-            ng = 0;
-            ++nrr;
-            if (nrr == nrows) {
-                nrr = 0;
-                nblk_i = blk + wave_stride;
+    for (int64_t blk = wave_gid; blk < nblk; blk += wave_stride) {
+        const int64_t row0 = blk * kRowsPerBlock;
+        const int nrows = (int)(a.n - row0 < kRowsPerBlock ? a.n - row0 : kRowsPerBlock);
+        if constexpr (CH <= 8) {
+            // two rows per step: the second row's loads overlap the first row's sums
+            Buf bufA, bufB;
+            for (int rr = 0; rr < nrows; rr += 2) {
+                const bool two = rr + 1 < nrows;
+                load_row(bufA, row0 + rr);
+                load_row(bufB, row0 + rr + (two ? 1 : 0));
+                process_row(bufA, row0 + rr, rr, nrows, row0);
+                if (two)
+                    process_row(bufB, row0 + rr + 1, rr + 1, nrows, row0);
+            }
+        } else {
+            Buf buf;
+            for (int rr = 0; rr < nrows; ++rr) {
+                load_row(buf, row0 + rr);
+                process_row(buf, row0 + rr, rr, nrows, row0);
             }
         }
-        const bool have_next = nblk_i < nblk;
-        if (have_next)
-            load(useA ? bufB : bufA, nblk_i * kRowsPerBlock + nrr, ng);
-
-        scatter(useA ? bufA : bufB, g);
-
-        if (g == ngroups - 1) {
-            // row complete: discretise and key
-            wave_sync();
-            const int64_t row = blk * kRowsPerBlock + rr;
-            if constexpr (FAM == LSH_E2LSH)
-                epilogue_e2lsh<DT, RECHECK>(a, tab, w, bl, hinit, row, rr, gam, nflag, nchg, nsat);
-            else
-                epilogue_srp<DT, RECHECK>(a, tab, w, row, rr, gam, nflag, nchg);
-            wave_sync();
-            for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4) {
-                *(float4 *)(w.bins + l) = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (RECHECK)
-                    *(float4 *)(w.absb + l) = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            if (rr == nrows - 1 && a.keys) {
-                // block complete: write the staged keys, 8 consecutive rows per table
-                const int64_t row0 = blk * kRowsPerBlock;
-                for (int e = lane; e < a.L * kRowsPerBlock; e += kWave) {
-                    int t = e / kRowsPerBlock, r = e % kRowsPerBlock;
-                    if (r < nrows)
-                        a.keys[(int64_t)t * a.key_ld + row0 + r] = w.stage[e];
-                }
-            }
-            wave_sync();
-        }
-        if (!have_next)
-            break;
-        if (nblk_i != blk)
-            nrows = rows_in(nblk_i);
-        blk = nblk_i;
-        rr = nrr;
-        g = ng;
-        useA = !useA;
     }
 
     if (a.counters) {
@@ -530,7 +606,10 @@ __global__ __launch_bounds__(1024) void csr_kernel(HashArgs a, uint32_t *off, ui
     if (tid == 0)
         smax = 0;
     for (int i = tid; i < p2; i += blockDim.x)
-        skeys[i] = i < a.d ? ((table_entry(a, i, bad) >> 1) << 16) | (uint32_t)i : 0xffffffffu;
+    {
+        uint32_t neg;
+        skeys[i] = i < a.d ? (table_bin(a, i, bad, neg) << 16) | (uint32_t)i : 0xffffffffu;
+    }
     __syncthreads();
     // bitonic sort of (bin, coordinate) pairs
     for (int k = 2; k <= p2; k <<= 1) {
@@ -597,10 +676,10 @@ WsLayout ws_layout(int32_t d, int32_t m)
 
 int esize(int dt) { return dt == LSH_F32 ? 4 : (dt == LSH_BF16 ? 2 : 1); }
 
-template <int FAM, int DT, bool AL, bool RC>
+template <int FAM, int DT, bool AL, bool RC, int CH>
 hipError_t launch_one(const HashArgs &a, int block, size_t lds, hipStream_t st, int64_t nblk)
 {
-    auto k = hash_kernel<FAM, DT, AL, RC>;
+    auto k = hash_kernel<FAM, DT, AL, RC, CH>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess)
@@ -618,28 +697,53 @@ hipError_t launch_one(const HashArgs &a, int block, size_t lds, hipStream_t st, 
     return hipGetLastError();
 }
 
+template <int FAM, int DT, bool AL, bool RC>
+hipError_t launch_ch(const HashArgs &a, int ch, int block, size_t lds, hipStream_t st, int64_t nblk)
+{
+    if constexpr (AL) {
+        switch (ch) {
+        case 1:
+            return launch_one<FAM, DT, AL, RC, 1>(a, block, lds, st, nblk);
+        case 2:
+            return launch_one<FAM, DT, AL, RC, 2>(a, block, lds, st, nblk);
+        case 4:
+            return launch_one<FAM, DT, AL, RC, 4>(a, block, lds, st, nblk);
+        case 8:
+            return launch_one<FAM, DT, AL, RC, 8>(a, block, lds, st, nblk);
+        case 16:
+            return launch_one<FAM, DT, AL, RC, 16>(a, block, lds, st, nblk);
+        default:
+            return launch_one<FAM, DT, AL, RC, 32>(a, block, lds, st, nblk);
+        }
+    } else {
+        if (ch <= 8)
+            return launch_one<FAM, DT, AL, RC, 8>(a, block, lds, st, nblk);
+        return launch_one<FAM, DT, AL, RC, 32>(a, block, lds, st, nblk);
+    }
+}
+
 template <int FAM, int DT>
-hipError_t launch_dt(const HashArgs &a, bool al, bool rc, int block, size_t lds, hipStream_t st,
-                     int64_t nblk)
+hipError_t launch_dt(const HashArgs &a, bool al, bool rc, int ch, int block, size_t lds,
+                     hipStream_t st, int64_t nblk)
 {
     if (al)
-        return rc ? launch_one<FAM, DT, true, true>(a, block, lds, st, nblk)
-                  : launch_one<FAM, DT, true, false>(a, block, lds, st, nblk);
-    return rc ? launch_one<FAM, DT, false, true>(a, block, lds, st, nblk)
-              : launch_one<FAM, DT, false, false>(a, block, lds, st, nblk);
+        return rc ? launch_ch<FAM, DT, true, true>(a, ch, block, lds, st, nblk)
+                  : launch_ch<FAM, DT, true, false>(a, ch, block, lds, st, nblk);
+    return rc ? launch_ch<FAM, DT, false, true>(a, ch, block, lds, st, nblk)
+              : launch_ch<FAM, DT, false, false>(a, ch, block, lds, st, nblk);
 }
 
 template <int FAM>
-hipError_t launch_fam(const HashArgs &a, int dt, bool al, bool rc, int block, size_t lds,
+hipError_t launch_fam(const HashArgs &a, int dt, bool al, bool rc, int ch, int block, size_t lds,
                       hipStream_t st, int64_t nblk)
 {
     switch (dt) {
     case LSH_F32:
-        return launch_dt<FAM, LSH_F32>(a, al, rc, block, lds, st, nblk);
+        return launch_dt<FAM, LSH_F32>(a, al, rc, ch, block, lds, st, nblk);
     case LSH_BF16:
-        return launch_dt<FAM, LSH_BF16>(a, al, rc, block, lds, st, nblk);
+        return launch_dt<FAM, LSH_BF16>(a, al, rc, ch, block, lds, st, nblk);
     default:
-        return launch_dt<FAM, LSH_FP8_E4M3FN>(a, al, rc, block, lds, st, nblk);
+        return launch_dt<FAM, LSH_FP8_E4M3FN>(a, al, rc, ch, block, lds, st, nblk);
     }
 }
 
@@ -694,8 +798,8 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
     lsh_status st;
     if ((st = check_points(pts)) != LSH_OK || (st = check_disc(disc)) != LSH_OK)
         return st;
-    if (disc->m > 32768)
-        LSH_FAIL(LSH_EINVAL, "m = %d exceeds 32768", disc->m);
+    if (disc->m > 16384)
+        LSH_FAIL(LSH_EINVAL, "m = %d exceeds 16384", disc->m);
     if (!out)
         LSH_FAIL(LSH_EINVAL, "output descriptor is NULL");
     const bool rc = disc->recheck != 0;
@@ -733,12 +837,23 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
     const int per16 = 16 / es;
     const bool al = ((uintptr_t)pts->x % 16 == 0) && ((pts->ld * es) % 16 == 0) &&
                     (pts->d % per16 == 0);
+    // a row is held in registers: at most 64 * 32 chunks (16-byte chunks when
+    // aligned, single elements otherwise)
+    const int64_t nch = al ? pts->d / per16 : pts->d;
+    int ch = 1;
+    while (ch < 32 && 64 * ch < nch)
+        ch <<= 1;
+    if (!al && ch < 8)
+        ch = 8;
+    if (64 * ch < nch)
+        LSH_FAIL(LSH_EINVAL, "d = %d exceeds the single-pass row size (%d elements%s)", pts->d,
+                 64 * 32 * (al ? per16 : 1), al ? "" : "; rows are not 16-byte aligned");
 
     // LDS layout
     a.tab_bytes = align16(pts->d * 2);
-    a.mpad = (int32_t)align_up((size_t)a.m, 256);
-    size_t shared = (size_t)a.tab_bytes + align16(a.m * 4) + align16(a.L * 16);
-    size_t per_wave = (size_t)a.mpad * 4 * (rc ? 2 : 1) + (size_t)a.L * kRowsPerBlock * 8 +
+    a.mpad = (int32_t)align_up((size_t)bin_pos(a.m), 256);
+    size_t shared = (size_t)a.tab_bytes + align16(bin_pos(a.m) * 4) + align16(a.L * 16);
+    size_t per_wave = (size_t)a.mpad * 4 + (size_t)a.L * kRowsPerBlock * 8 +
                       align16(((a.m + 63) / 64) * 8);
     a.wave_bytes = (int32_t)align_up(per_wave, 16);
     const size_t lds_max = 160 * 1024;
@@ -758,7 +873,7 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         if (!ws || ws_bytes < wl.total)
             LSH_FAIL(LSH_ENOMEM, "recheck workspace needs %zu bytes, got %zu", wl.total, ws_bytes);
         unsigned char *wb = (unsigned char *)ws;
-        a.cmax = (const uint32_t *)(wb + wl.cmax);
+        uint32_t *cmax_ws = (uint32_t *)(wb + wl.cmax);
         a.csr_off = (const uint32_t *)(wb + wl.off);
         a.csr_idx = (const uint32_t *)(wb + wl.idx);
         int p2 = 1;
@@ -768,13 +883,13 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         LSH_HIP(hipFuncSetAttribute((const void *)csr_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)clds));
         hipLaunchKernelGGL(csr_kernel, dim3(1), dim3(1024), clds, s, a, (uint32_t *)a.csr_off,
-                           (uint32_t *)a.csr_idx, (uint32_t *)a.cmax, p2);
+                           (uint32_t *)a.csr_idx, cmax_ws, p2);
         LSH_LAUNCHED("csr_kernel");
     }
 
     hipError_t e = disc->family == LSH_E2LSH
-                       ? launch_fam<LSH_E2LSH>(a, pts->dtype, al, rc, waves * kWave, lds, s, nblk)
-                       : launch_fam<LSH_SRP>(a, pts->dtype, al, rc, waves * kWave, lds, s, nblk);
+                       ? launch_fam<LSH_E2LSH>(a, pts->dtype, al, rc, ch, waves * kWave, lds, s, nblk)
+                       : launch_fam<LSH_SRP>(a, pts->dtype, al, rc, ch, waves * kWave, lds, s, nblk);
     if (e != hipSuccess)
         LSH_FAIL(LSH_EHIP, "hash kernel launch failed: %s", hip_msg(e));
     return LSH_OK;
