@@ -123,7 +123,7 @@ size_t lsh_hash_workspace_bytes(int32_t d, int32_t m, int32_t recheck);
  * cs_consine_lsh): y_l = sum over j with h[j] = l of s[j] * x_j, then the
  * family's discretisation, codes and keys.
  *   h: [d] bins in [0, m); s: [d] signs, each +1 or -1.
- * Requires m <= 32768.  EINVAL on bad shapes, ENOMEM if ws_bytes is short. */
+ * Requires m <= 16384.  EINVAL on bad shapes, ENOMEM if ws_bytes is short. */
 lsh_status lsh_hash_cs(const lsh_points *pts, const uint32_t *h, const int8_t *s,
                        const lsh_disc *disc, const lsh_out *out, void *workspace,
                        size_t ws_bytes, void *stream);

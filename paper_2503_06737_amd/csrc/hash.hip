@@ -27,8 +27,10 @@
 //     than c * 2^-k for a bin of c terms;
 //   * after a row, the wave discretises its bins (E2LSH: one lane per table,
 //     bins padded one word per 16 so those reads are conflict-free; SRP: one
-//     lane per component plus ballots) and stages the L keys of its RB rows
-//     in LDS, so key stores leave as 8-key (64-byte) runs.
+//     lane per component plus ballots) and stores the row's L keys; a wave's
+//     consecutive rows fill the same 64-byte key lines in L2 before they are
+//     written back.  LDS per wave is just the bins, so three 8-wave
+//     workgroups fit on a CU.
 // The optional FP64 recheck recomputes, in ascending coordinate order and in
 // FP64, every component whose value lies within the rigorous bound of its
 // error from a bin edge (E2LSH) or from zero (SRP).
@@ -41,7 +43,9 @@
 
 namespace lsh {
 
-constexpr int kRowsPerBlock = 8; // RB: rows a wave hashes before writing keys
+// RB: consecutive rows a workgroup hashes before it writes their keys; a
+// table's RB keys fill two 128-byte lines
+constexpr int kRowsPerBlock = 32;
 constexpr int kMaxModes = 8;
 
 __host__ __device__ constexpr int align16(int v) { return (v + 15) & ~15; }
@@ -49,6 +53,9 @@ __host__ __device__ constexpr int align16(int v) { return (v + 15) & ~15; }
 // LDS slot of sketch bin l: one pad word after every 16 bins, so that lanes
 // reading K consecutive bins each (one lane per table) hit distinct banks.
 __host__ __device__ constexpr int bin_pos(int l) { return l + (l >> 4); }
+// Bin slots [bin_pos(m), bin_pos(m) + 64) are per-lane trash: a lane with
+// nothing to add adds there, at its own address (no same-address atomics).
+constexpr int kTrashSlots = kWave;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -82,11 +89,37 @@ struct HashArgs {
     const uint32_t *csr_off;
     const uint32_t *csr_idx;
     // layout
-    int32_t waves;      // waves per workgroup
-    int32_t tab_bytes;  // LDS bytes of the hash table (aligned)
-    int32_t mpad;       // bin slots per wave, multiple of 256
-    int32_t wave_bytes; // LDS bytes per wave
+    int32_t waves;       // waves per workgroup
+    int32_t mpad;        // bin slots per wave (bins, pad words, trash), multiple of 4
+    int32_t wave_region; // LDS bytes per wave region: a power of two >= 4 * mpad
+    int32_t tab_entries; // table entries: 64 * CH * VEC (rows padded to whole chunks)
+    int32_t tab_off, bl_off, hinit_off, mask_off; // LDS byte offsets
+    // key staging (stage_stride 0: keys are stored straight to memory):
+    // key of table t for row slot i of the block is at LDS byte
+    // stage_base + (t >> stage_tpc_log2) * stage_stride
+    //            + ((t & (2^stage_tpc_log2 - 1)) * (RB + 1) + i) * 8
+    int32_t stage_base, stage_stride, stage_tpc_log2;
 };
+
+__device__ __forceinline__ uint32_t stage_addr(const HashArgs &a, int t, int slot)
+{
+    const uint32_t tpc_mask = (1u << a.stage_tpc_log2) - 1u;
+    return (uint32_t)a.stage_base + ((uint32_t)t >> a.stage_tpc_log2) * (uint32_t)a.stage_stride +
+           (((uint32_t)t & tpc_mask) * (kRowsPerBlock + 1) + (uint32_t)slot) * 8u;
+}
+
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+
+// Key of table t for `row` (slot `slot` of its block): staged in LDS for the
+// workgroup's coalesced write-out, or stored directly.
+__device__ __forceinline__ void emit_key(const HashArgs &a, int t, int64_t row, int slot,
+                                         uint64_t key)
+{
+    if (a.stage_stride)
+        *(lds_u64 *)(size_t)stage_addr(a, t, slot) = key;
+    else
+        a.keys[(int64_t)t * a.key_ld + row] = key;
+}
 
 // Bin of coordinate j in the sketch and its sign (neg = sign < 0).
 __device__ __forceinline__ uint32_t table_bin(const HashArgs &a, int32_t j, bool &bad,
@@ -124,12 +157,14 @@ __device__ __forceinline__ uint32_t table_bin(const HashArgs &a, int32_t j, bool
     return bin;
 }
 
-// Packed LDS table entry of coordinate j: LDS slot of its bin << 1 | sign bit.
+// LDS table entry of coordinate j: byte offset of its bin's slot inside a
+// wave's region, sign in bit 31.  A lane forms the LDS address of the slot
+// with one v_and_or (offset bits | its wave's region base).
 __device__ __forceinline__ uint32_t table_entry(const HashArgs &a, int32_t j, bool &bad)
 {
     uint32_t neg;
     uint32_t bin = table_bin(a, j, bad, neg);
-    return ((uint32_t)bin_pos((int)bin) << 1) | neg;
+    return ((uint32_t)bin_pos((int)bin) * 4u) | (neg << 31);
 }
 
 // ----------------------------------------------------------------- decoding
@@ -194,10 +229,17 @@ template <int DT> __device__ __forceinline__ float scalar_value(const void *x, i
 
 // ----------------------------------------------------------- wave helpers
 
+// Integer add into the LDS word at byte address addr (an address-space-3
+// pointer built from the integer, so no symbol offset is added per access).
+__device__ __forceinline__ void lds_add_i32(uint32_t addr, int32_t v)
+{
+    typedef __attribute__((address_space(3))) int32_t lds_i32;
+    __atomic_fetch_add((lds_i32 *)(size_t)addr, v, __ATOMIC_RELAXED);
+}
+
 struct WaveLds {
-    int32_t *bins;   // [mpad] fixed-point sums, indexed by bin_pos
-    uint64_t *stage; // [L * RB] keys of the current row block
-    uint64_t *mask;  // [ceil(m/64)] SRP sign bits of the current row
+    int32_t *bins;   // [mpad] this wave's fixed-point sums, indexed by bin_pos
+    uint64_t *mask;  // [ceil(m/64)] this wave's SRP sign bits of the current row
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -206,12 +248,18 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ float wave_max(float v)
+// Maximum of a non-negative value over the wave with DPP (no LDS round
+// trips): prefix maxima inside each row of 16 lanes (row_shr 1, 2, 4, 8),
+// then row_bcast 15 and 31 carry them to lane 63.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Per-row scale (1 for FP32 points), read through the scalar cache: row is
@@ -239,7 +287,7 @@ struct RowFix {
 // Exact FP64 value of component l of row `row`, summed in ascending
 // coordinate order exactly as an FP64 evaluation of the definition would.
 template <int DT>
-__device__ double exact_component(const HashArgs &a, const uint16_t *tab, int64_t row, double scale,
+__device__ double exact_component(const HashArgs &a, const uint32_t *tab, int64_t row, double scale,
                                   int32_t l)
 {
     double y = 0.0;
@@ -247,7 +295,7 @@ __device__ double exact_component(const HashArgs &a, const uint16_t *tab, int64_
     for (uint32_t p = p0; p < p1; ++p) {
         uint32_t j = a.csr_idx[p];
         double xv = __dmul_rn(scale, (double)scalar_value<DT>(a.x, row * a.ld + j));
-        y = __dadd_rn(y, (tab[j] & 1u) ? -xv : xv);
+        y = __dadd_rn(y, (tab[j] >> 31) ? -xv : xv);
     }
     return y;
 }
@@ -256,7 +304,7 @@ __device__ double exact_component(const HashArgs &a, const uint16_t *tab, int64_
 
 // Code of E2LSH component l (Definition CS_Eucl_LSH): floor((sqrt(m) y + b)/w).
 template <int DT, bool RECHECK>
-__device__ __forceinline__ int32_t e2lsh_code(const HashArgs &a, const uint16_t *tab,
+__device__ __forceinline__ int32_t e2lsh_code(const HashArgs &a, const uint32_t *tab,
                                               const WaveLds &w, const float *bl, int64_t row,
                                               const RowFix &rf, int32_t l, bool count,
                                               unsigned &nflag, unsigned &nchg, unsigned &nsat)
@@ -266,10 +314,9 @@ __device__ __forceinline__ int32_t e2lsh_code(const HashArgs &a, const uint16_t 
     double cd;
     if constexpr (!RECHECK) {
         // bl holds b / w here; the row factor sqrt(m) * scale * 2^-k / w is folded in
+        // (the projection output is written by the caller on this path)
         float v = fmaf(rf.af, (float)isum, bl[pl]);
         cd = (double)floorf(v);
-        if (a.proj && count)
-            a.proj[row * a.m + l] = (float)isum * rf.fs;
     } else {
         double y64 = (double)isum * rf.s2k;
         double t = __dmul_rn(a.alpha64, y64);
@@ -301,12 +348,161 @@ __device__ __forceinline__ int32_t e2lsh_code(const HashArgs &a, const uint16_t 
     return ci;
 }
 
+// floor(v) as int32 in one instruction (v_cvt_flr_i32_f32); callers pass
+// values well inside the int32 range.
+__device__ __forceinline__ int32_t cvt_flr_i32(float v)
+{
+    int32_t r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+// Key of table t for a row whose codes are all known to lie in [-128, 127]
+// (the caller's bound): code = floor(af * sum + b/w), the same FP32 value as
+// the checked path, packed as two's-complement bytes with v_perm and mixed
+// 8 codes per word (the narrow form of the key definition).
+template <int KC>
+__device__ __forceinline__ uint64_t e2lsh_narrow_key(const WaveLds &w, const float *bl,
+                                                     const uint64_t *hinit, int t, float af)
+{
+    const int32_t l0 = t * KC;
+    uint64_t h = hinit[2 * t];
+#pragma unroll
+    for (int q = 0; q < KC / 8; ++q) {
+        uint32_t wd[2];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            int32_t c[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pl = bin_pos(l0 + 8 * q + 4 * hh + r);
+                c[r] = cvt_flr_i32(fmaf(af, (float)w.bins[pl], bl[pl]));
+            }
+            const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)c[1], (uint32_t)c[0], 0x0c0c0400u);
+            const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)c[3], (uint32_t)c[2], 0x0c0c0400u);
+            wd[hh] = __builtin_amdgcn_perm(p23, p01, 0x05040100u);
+        }
+        h = mix64(h ^ (((uint64_t)wd[1] << 32) | (uint64_t)wd[0]));
+    }
+    return h;
+}
+
+// SRP key of table t from the signs of its K bins: bit r = [sum > 0], taken
+// as med3(sum, 0, 1) and or-ed in place (two instructions per bit).
+template <int KC>
+__device__ __forceinline__ uint64_t srp_key(const WaveLds &w, int t)
+{
+    const int32_t l0 = t * KC;
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int r = 0; r < KC; ++r) {
+        const int32_t isum = w.bins[bin_pos(l0 + r)];
+        const uint32_t bit = (uint32_t)min(max(isum, 0), 1);
+        if (r < 32)
+            lo |= bit << r;
+        else
+            hi |= bit << (r - 32);
+    }
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+__device__ __forceinline__ uint64_t srp_key_any(const HashArgs &a, const WaveLds &w, int t)
+{
+    const int32_t l0 = t * a.K;
+    uint64_t v = 0;
+    for (int r = 0; r < a.K; ++r) {
+        const int32_t isum = w.bins[bin_pos(l0 + r)];
+        v |= (uint64_t)(uint32_t)min(max(isum, 0), 1) << r;
+    }
+    return v;
+}
+
+// Fast-path table key (no recheck), K known at compile time.  Codes are
+// floor(af * sum + b/w) with af = sqrt(m) * scale * 2^-k / w folded into one
+// FMA; narrow tuples (all codes in [-128, 127], the common case) are packed
+// four codes per dword with v_cvt_pk_u8_f32 on code + 128 (then XOR 0x80
+// per byte gives the two's-complement byte of the key definition).
+template <int KC>
+__device__ __forceinline__ uint64_t e2lsh_fast_key(const HashArgs &a, const WaveLds &w,
+                                                   const float *bl, const uint64_t *hinit, int t,
+                                                   float af, int64_t row, unsigned &nsat)
+{
+    const int32_t l0 = t * KC;
+    float c[KC];
+#pragma unroll
+    for (int r = 0; r < KC; ++r) {
+        const int pl = bin_pos(l0 + r);
+        c[r] = floorf(fmaf(af, (float)w.bins[pl], bl[pl]));
+    }
+    float mn = c[0], mx = c[0];
+#pragma unroll
+    for (int r = 1; r < KC; ++r) {
+        mn = fminf(mn, c[r]);
+        mx = fmaxf(mx, c[r]);
+    }
+    if (a.codes) {
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            unsigned s2 = 0;
+            a.codes[row * a.m + l0 + r] = floor_to_i32((double)c[r], s2);
+        }
+    }
+    if (mn >= -128.0f && mx <= 127.0f) {
+        uint64_t h = hinit[2 * t];
+#pragma unroll
+        for (int q = 0; q < KC / 8; ++q) {
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                lo = __builtin_amdgcn_cvt_pk_u8_f32(c[8 * q + r] + 128.0f, r, lo);
+                hi = __builtin_amdgcn_cvt_pk_u8_f32(c[8 * q + 4 + r] + 128.0f, r, hi);
+            }
+            const uint64_t W = ((uint64_t)(hi ^ 0x80808080u) << 32) | (uint64_t)(lo ^ 0x80808080u);
+            h = mix64(h ^ W);
+        }
+        return h;
+    }
+    // wide tuple (rare): 32-bit codes, saturated to int32
+    return e2lsh_key(KC, hinit[2 * t], hinit[2 * t + 1], [&](int r, bool first) {
+        unsigned s2 = 0;
+        int32_t ci = floor_to_i32((double)c[r], s2);
+        if (first)
+            nsat += s2;
+        return ci;
+    });
+}
+
 template <int DT, bool RECHECK>
-__device__ void epilogue_e2lsh(const HashArgs &a, const uint16_t *tab, const WaveLds &w,
-                               const float *bl, const uint64_t *hinit, int64_t row, int rr,
-                               const RowFix &rf, unsigned &nflag, unsigned &nchg, unsigned &nsat)
+__device__ void epilogue_e2lsh(const HashArgs &a, const uint32_t *tab, const WaveLds &w,
+                               const float *bl, const uint64_t *hinit, int64_t row, int slot,
+                               const RowFix &rf, bool narrow, unsigned &nflag, unsigned &nchg,
+                               unsigned &nsat)
 {
     const int lane = lane_id();
+    if constexpr (!RECHECK) {
+        if (a.proj) {
+            for (int32_t l = lane; l < a.m; l += kWave)
+                a.proj[row * a.m + l] = (float)w.bins[bin_pos(l)] * rf.fs;
+        }
+        if (narrow && !a.codes && (a.K == 16 || a.K == 8)) {
+            for (int t = lane; t < a.L; t += kWave) {
+                const uint64_t key = a.K == 16 ? e2lsh_narrow_key<16>(w, bl, hinit, t, rf.af)
+                                               : e2lsh_narrow_key<8>(w, bl, hinit, t, rf.af);
+                if (a.keys)
+                    emit_key(a, t, row, slot, key);
+            }
+            return;
+        }
+        if (a.K == 16 || a.K == 8) {
+            for (int t = lane; t < a.L; t += kWave) {
+                uint64_t key = a.K == 16 ? e2lsh_fast_key<16>(a, w, bl, hinit, t, rf.af, row, nsat)
+                                         : e2lsh_fast_key<8>(a, w, bl, hinit, t, rf.af, row, nsat);
+                if (a.keys)
+                    emit_key(a, t, row, slot, key);
+            }
+            return;
+        }
+    }
     for (int t = lane; t < a.L; t += kWave) {
         const int32_t l0 = t * a.K;
         uint64_t key = e2lsh_key(a.K, hinit[2 * t], hinit[2 * t + 1], [&](int r, bool first) {
@@ -316,25 +512,49 @@ __device__ void epilogue_e2lsh(const HashArgs &a, const uint16_t *tab, const Wav
                 a.codes[row * a.m + l0 + r] = c;
             return c;
         });
-        w.stage[t * kRowsPerBlock + rr] = key;
+        if (a.keys)
+            emit_key(a, t, row, slot, key);
     }
 }
 
 // SRP family: bit = [y > 0] (Definition cs_consine_lsh).  The fixed-point sum
 // has the sign of y except within its error bound of 0 (rechecked on request).
 template <int DT, bool RECHECK>
-__device__ void epilogue_srp(const HashArgs &a, const uint16_t *tab, const WaveLds &w, int64_t row,
-                             int rr, const RowFix &rf, unsigned &nflag, unsigned &nchg)
+__device__ void epilogue_srp(const HashArgs &a, const uint32_t *tab, const WaveLds &w, int64_t row,
+                             int slot, const RowFix &rf, unsigned &nflag, unsigned &nchg)
 {
     const int lane = lane_id();
+    if constexpr (!RECHECK) {
+        if (!a.codes && !a.proj) {
+            if (a.keys) {
+                for (int t = lane; t < a.L; t += kWave) {
+                    uint64_t v;
+                    if (a.K == 16)
+                        v = srp_key<16>(w, t);
+                    else if (a.K == 8)
+                        v = srp_key<8>(w, t);
+                    else if (a.K == 32)
+                        v = srp_key<32>(w, t);
+                    else
+                        v = srp_key_any(a, w, t);
+                    emit_key(a, t, row, slot, v);
+                }
+            }
+            return;
+        }
+    }
     const int ngroups = (a.m + kWave - 1) / kWave;
+    // ballot of group g is kept by lane g % 64 and written out every 64 groups
+    uint64_t mine = 0;
     for (int g = 0; g < ngroups; ++g) {
         int32_t l = g * kWave + lane;
         bool bit = false;
         if (l < a.m) {
             const int32_t isum = w.bins[bin_pos(l)];
             bit = isum > 0;
-            float yout = (float)isum * rf.fs;
+            float yout = 0.0f;
+            if (a.proj)
+                yout = (float)isum * rf.fs;
             if constexpr (RECHECK) {
                 double y64 = (double)isum * rf.s2k;
                 double Ey = rf.ey + fabs(y64) * 0x1.0p-51;
@@ -353,9 +573,12 @@ __device__ void epilogue_srp(const HashArgs &a, const uint16_t *tab, const WaveL
             if (a.proj)
                 a.proj[row * a.m + l] = yout;
         }
-        uint64_t bal = __ballot(bit);
-        if (lane == 0)
-            w.mask[g] = bal;
+        const uint64_t bal = __ballot(bit);
+        mine = lane == (g & (kWave - 1)) ? bal : mine;
+        if ((g & (kWave - 1)) == kWave - 1 || g == ngroups - 1) {
+            if (lane <= (g & (kWave - 1)))
+                w.mask[(g & ~(kWave - 1)) + lane] = mine;
+        }
     }
     wave_sync();
     for (int t = lane; t < a.L; t += kWave) {
@@ -365,48 +588,64 @@ __device__ void epilogue_srp(const HashArgs &a, const uint16_t *tab, const WaveL
             v |= w.mask[(s0 >> 6) + 1] << (64 - (s0 & 63));
         if (a.K < 64)
             v &= (1ull << a.K) - 1ull;
-        w.stage[t * kRowsPerBlock + rr] = v;
+        if (a.keys)
+            emit_key(a, t, row, slot, v);
     }
 }
 
 // ------------------------------------------------------------------ kernel
 
+template <int DT, bool ALIGNED> constexpr int ALIGNED_VEC() { return ALIGNED ? Elem<DT>::per16 : 1; }
+
 // CH: 16-byte chunks (ALIGNED) or single elements per lane per row; a row
 // has at most 64 * CH of them.
+//
+// LDS image of a workgroup (offsets in HashArgs):
+//   [wave regions: waves x wave_region bytes, each holding mpad int32 bins]
+//   [table: tab_entries u32] [b/w or b: bin_pos(m) floats] [digest seeds]
+//   [SRP masks: waves x ceil(m/64) u64]
 template <int FAM, int DT, bool ALIGNED, bool RECHECK, int CH>
-__global__ __launch_bounds__(512) void hash_kernel(HashArgs a)
+// small rows: registers capped so that two workgroups fit per CU (the LDS
+// limit); long rows keep their whole row in registers instead
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CH * ALIGNED_VEC<DT, ALIGNED>() <= 16 ? 4 : 1)))
+void hash_kernel(HashArgs a)
 {
+    // (the kernel has no static LDS, so this array starts at LDS address 0
+    // and byte offsets into it are LDS addresses)
     extern __shared__ __align__(16) unsigned char lds[];
-    uint16_t *tab = (uint16_t *)lds;
-    float *bl = (float *)(lds + a.tab_bytes);
-    uint64_t *hinit = (uint64_t *)(lds + a.tab_bytes + align16(bin_pos(a.m) * 4));
-    unsigned char *wave_base = lds + a.tab_bytes + align16(bin_pos(a.m) * 4) + align16(a.L * 16);
-    __shared__ uint32_t s_cmax;
+    const uint32_t *tab = (const uint32_t *)(lds + a.tab_off);
+    float *bl = (float *)(lds + a.bl_off);
+    uint64_t *hinit = (uint64_t *)(lds + a.hinit_off);
 
     const int tid = threadIdx.x;
     // wave index, made visibly uniform so the row cursor lives in SGPRs
     const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int lane = lane_id();
+    constexpr int VEC = ALIGNED ? Elem<DT>::per16 : 1;
 
     WaveLds w;
-    unsigned char *mine = wave_base + (size_t)wid * a.wave_bytes;
-    w.bins = (int32_t *)mine;
-    w.stage = (uint64_t *)(mine + a.mpad * 4);
-    w.mask = w.stage + a.L * kRowsPerBlock;
+    const uint32_t region = (uint32_t)wid * (uint32_t)a.wave_region; // this wave's base
+    w.bins = (int32_t *)(lds + region);
+    w.mask = (uint64_t *)(lds + a.mask_off) + (size_t)wid * ((a.m + 63) / 64);
 
-    // ---- prologue: zero every wave's bins; wave 0's bins first count the
-    // bin populations (integer LDS atomics) to find c_max
-    if (tid == 0)
-        s_cmax = 0;
+    // ---- prologue: zero every bin; build the table (rows padded to whole
+    // chunks: coordinates past d point at their lane's trash slot); count
+    // the bin populations in wave 0's region to get c_max; zero again
+    const int nwv = blockDim.x / kWave;
     for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4)
         *(int4 *)(w.bins + l) = make_int4(0, 0, 0, 0);
     __syncthreads();
-    int32_t *cnt = (int32_t *)wave_base;
     bool bad = false;
-    for (int32_t j = tid; j < a.d; j += blockDim.x) {
-        uint32_t ent = table_entry(a, j, bad);
-        tab[j] = (uint16_t)ent;
-        atomicAdd(&cnt[ent >> 1], 1);
+    uint32_t *tabw = (uint32_t *)(lds + a.tab_off);
+    for (int32_t j = tid; j < a.tab_entries; j += blockDim.x) {
+        uint32_t ent;
+        if (j < a.d) {
+            ent = table_entry(a, j, bad);
+            atomicAdd((int32_t *)(lds + (ent & 0x7fffffffu)), 1);
+        } else {
+            ent = (uint32_t)(bin_pos(a.m) + (j / VEC) % kWave) * 4u;
+        }
+        tabw[j] = ent;
     }
     if (FAM == LSH_E2LSH) {
         // fast path: b / w (the row factor folds 1/w in); recheck: b as given
@@ -416,26 +655,26 @@ __global__ __launch_bounds__(512) void hash_kernel(HashArgs a)
             hinit[t] = mix64((uint64_t)t); // = F(2 * table + wide)
     }
     __syncthreads();
-    for (int32_t l = tid; l < a.m; l += blockDim.x)
-        atomicMax(&s_cmax, (uint32_t)cnt[bin_pos(l)]);
+    uint32_t cm = 0;
+    for (int32_t l = lane; l < a.m; l += kWave)
+        cm = max(cm, (uint32_t)((const int32_t *)lds)[bin_pos(l)]);
+    const uint32_t cmax = wave_max_u32(cm);
     __syncthreads();
-    for (int32_t l = tid; l < a.mpad; l += blockDim.x)
-        cnt[l] = 0;
+    if (wid == 0)
+        for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4)
+            *(int4 *)(w.bins + l) = make_int4(0, 0, 0, 0);
     if (bad && a.counters && tid == 0)
         atomicAdd(&a.counters[3], 1ull);
     __syncthreads();
+    (void)nwv;
 
-    const uint32_t cmax = s_cmax;
     // terms are kept below 2^(31 - hr) with c_max < 2^hr: no bin overflows int32
     const int hr = cmax ? 32 - __clz(cmax) : 0;
     const int koff = 31 - hr;
 
     // ---- rows owned by this wave
-    constexpr int VEC = ALIGNED ? Elem<DT>::per16 : 1;
-    const int64_t nblk = (a.n + kRowsPerBlock - 1) / kRowsPerBlock;
-    const int64_t wave_gid = (int64_t)blockIdx.x * a.waves + wid;
-    const int64_t wave_stride = (int64_t)gridDim.x * a.waves;
     const int32_t nchunk = a.d / VEC; // d % VEC == 0 when ALIGNED
+    const uint32_t offmask = (uint32_t)a.wave_region - 1u;
 
     unsigned nflag = 0, nchg = 0, nsat = 0;
 
@@ -443,8 +682,8 @@ __global__ __launch_bounds__(512) void hash_kernel(HashArgs a)
     using Buf = u32x4[CH];
 
     // Every lane issues exactly CH loads per row (chunks past the row end
-    // re-read chunk 0 and are not summed), so the number of loads in flight
-    // is static and each wait covers only the row being summed.
+    // re-read chunk 0 and are summed into trash), so the number of loads in
+    // flight is static and each wait covers only the row being summed.
     auto load_row = [&](Buf &buf, int64_t row) {
         const T *xr = (const T *)a.x + row * a.ld;
 #pragma unroll
@@ -464,56 +703,74 @@ __global__ __launch_bounds__(512) void hash_kernel(HashArgs a)
         }
     };
 
-    constexpr int TW = VEC >= 2 ? VEC / 2 : 1; // table dwords per chunk
-    auto process_row = [&](const Buf &buf, int64_t row, int rr, int nrows, int64_t row0) {
+    // table entries of this lane's chunks: kept in registers for the whole
+    // kernel when there are at most 16 per lane
+    auto load_entries = [&](int i, uint32_t *tw) {
+        const uint32_t *te = tab + (i * kWave + lane) * VEC;
+        if constexpr (VEC == 1) {
+            tw[0] = te[0];
+        } else {
+#pragma unroll
+            for (int q = 0; q < VEC / 4; ++q) {
+                u32x4 v = *(const u32x4 *)(te + 4 * q);
+                tw[4 * q + 0] = v[0];
+                tw[4 * q + 1] = v[1];
+                tw[4 * q + 2] = v[2];
+                tw[4 * q + 3] = v[3];
+            }
+        }
+    };
+    constexpr bool kTabRegs = CH * VEC <= 16;
+    uint32_t treg[kTabRegs ? CH * VEC : 1];
+    if constexpr (kTabRegs) {
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            load_entries(i, treg + i * VEC);
+    }
+
+    auto process_row = [&](const Buf &buf, int64_t row, int slot) {
         // 1. the row's largest magnitude -> exponent e (|x| < 2^e) -> k
         float mx = 0.0f;
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            if (i * kWave + lane < nchunk) {
+        for (int i = 0; i < CH; ++i)
 #pragma unroll
-                for (int e = 0; e < VEC; ++e)
-                    mx = fmaxf(mx, fabsf(chunk_value<DT, ALIGNED>(buf[i], e)));
-            }
-        }
-        const uint32_t mb = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_int(wave_max(mx)));
+            for (int e = 0; e < VEC; ++e)
+                mx = fmaxf(mx, fabsf(chunk_value<DT, ALIGNED>(buf[i], e)));
+        const uint32_t mb = wave_max_u32(__float_as_uint(mx));
         const int be = (int)((mb >> 23) & 0xffu);
         const int e = be == 0 ? -126 : be - 126;
         const int k = koff - e;
 
-        // 2. signed fixed-point sums into this wave's bins
+        // 2. signed fixed-point sums into this wave's bins: per element one
+        // v_and_or (slot address), one XOR (sign), ldexp, convert, LDS add.
+        // Entries come from registers (small rows) or are read one chunk
+        // ahead of the adds (LDS returns in order, so waiting for a read
+        // issued before the adds does not wait for the adds).
+        auto add_chunk = [&](int i, const uint32_t *tw) {
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int32_t ch = i * kWave + lane;
-            if (ch < nchunk) {
-                uint32_t tw[TW];
-                if constexpr (VEC == 1) {
-                    tw[0] = tab[ch];
-                } else if constexpr (VEC == 4) {
-                    uint2 v = *(const uint2 *)(tab + ch * VEC);
-                    tw[0] = v.x;
-                    tw[1] = v.y;
-                } else {
+            for (int e2 = 0; e2 < VEC; ++e2) {
+                const uint32_t ent = tw[e2];
+                const float v = chunk_value<DT, ALIGNED>(buf[i], e2);
+                const float sv = __uint_as_float(__float_as_uint(v) ^ (ent & 0x80000000u));
+                lds_add_i32((ent & offmask) | region, (int32_t)ldexpf(sv, k));
+            }
+        };
+        if constexpr (kTabRegs) {
 #pragma unroll
-                    for (int q = 0; q < TW / 4; ++q) {
-                        u32x4 v = *(const u32x4 *)(tab + ch * VEC + q * 8);
-                        tw[4 * q + 0] = v[0];
-                        tw[4 * q + 1] = v[1];
-                        tw[4 * q + 2] = v[2];
-                        tw[4 * q + 3] = v[3];
-                    }
-                }
+            for (int i = 0; i < CH; ++i)
+                add_chunk(i, treg + i * VEC);
+        } else {
+            uint32_t tw[2][VEC];
+            load_entries(0, tw[0]);
 #pragma unroll
-                for (int e2 = 0; e2 < VEC; ++e2) {
-                    uint32_t ent = VEC == 1 ? tw[0] : (tw[e2 >> 1] >> (16 * (e2 & 1))) & 0xffffu;
-                    float v = chunk_value<DT, ALIGNED>(buf[i], e2);
-                    float sv = __uint_as_float(__float_as_uint(v) ^ ((ent & 1u) << 31));
-                    atomicAdd(&w.bins[ent >> 1], (int32_t)ldexpf(sv, k));
-                }
+            for (int i = 0; i < CH; ++i) {
+                if (i + 1 < CH)
+                    load_entries(i + 1, tw[(i + 1) & 1]);
+                add_chunk(i, tw[i & 1]);
             }
         }
 
-        // 3. discretise, key, stage
+        // 3. discretise and key
         wave_sync();
         RowFix rf;
         rf.scale = row_scale_of<DT>(a, row);
@@ -529,44 +786,70 @@ __global__ __launch_bounds__(512) void hash_kernel(HashArgs a)
         } else {
             rf.ey = 0.0;
         }
+        // every code lies in [-128, 127] when sqrt(m) * scale * c_max * max|x| / w
+        // < 126: |sum| <= c_max * max|x| * 2^k (terms truncate toward zero)
+        // and b/w is in [0, 1); the margin covers the FP32 rounding of the bound
+        const bool narrow = a.alpha32 * rf.scale * (float)cmax * __uint_as_float(mb) * a.inv_w32 <
+                            126.0f;
         if constexpr (FAM == LSH_E2LSH)
-            epilogue_e2lsh<DT, RECHECK>(a, tab, w, bl, hinit, row, rr, rf, nflag, nchg, nsat);
+            epilogue_e2lsh<DT, RECHECK>(a, tab, w, bl, hinit, row, slot, rf, narrow, nflag, nchg,
+                                        nsat);
         else
-            epilogue_srp<DT, RECHECK>(a, tab, w, row, rr, rf, nflag, nchg);
+            epilogue_srp<DT, RECHECK>(a, tab, w, row, slot, rf, nflag, nchg);
         wave_sync();
         for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4)
             *(int4 *)(w.bins + l) = make_int4(0, 0, 0, 0);
-        if (rr == nrows - 1 && a.keys) {
-            // block complete: write the staged keys, up to 8 consecutive rows per table
-            for (int ee = lane; ee < a.L * kRowsPerBlock; ee += kWave) {
-                int t = ee / kRowsPerBlock, r = ee % kRowsPerBlock;
-                if (r < nrows)
-                    a.keys[(int64_t)t * a.key_ld + row0 + r] = w.stage[ee];
-            }
-        }
         wave_sync();
     };
 
-    for (int64_t blk = wave_gid; blk < nblk; blk += wave_stride) {
-        const int64_t row0 = blk * kRowsPerBlock;
-        const int nrows = (int)(a.n - row0 < kRowsPerBlock ? a.n - row0 : kRowsPerBlock);
-        if constexpr (CH <= 8) {
-            // two rows per step: the second row's loads overlap the first row's sums
-            Buf bufA, bufB;
-            for (int rr = 0; rr < nrows; rr += 2) {
-                const bool two = rr + 1 < nrows;
-                load_row(bufA, row0 + rr);
-                load_row(bufB, row0 + rr + (two ? 1 : 0));
-                process_row(bufA, row0 + rr, rr, nrows, row0);
-                if (two)
-                    process_row(bufB, row0 + rr + 1, rr + 1, nrows, row0);
+    // Rows: the workgroup takes blocks of RB consecutive rows, blocks strided
+    // by the grid; wave w of the workgroup takes rows w, w + waves, ... of
+    // each block, so all waves of the GPU read one contiguous window of X
+    // that slides forward.  The keys of a block are staged in LDS and, after
+    // a workgroup barrier, written as 256-byte runs per table (one store
+    // instruction covers two tables): storing each row's L keys straight
+    // from the lanes would touch L pages and L lines per instruction.
+    // Row r' (the wave's next) is loaded before row r is processed (two
+    // register buffers, alternated by unrolling the loop twice: RB / waves
+    // is even); every load is unconditional, rows past the end re-read row
+    // n - 1.  The cursor is kept in 32-bit scalars (n < 2^30 is checked on
+    // the host).  Every wave runs every block of its workgroup, so the
+    // barriers are uniform.
+    const int32_t n32 = (int32_t)a.n;
+    const int32_t per_wave = kRowsPerBlock / a.waves;
+    const int32_t nblk = (n32 + kRowsPerBlock - 1) / kRowsPerBlock;
+    const bool staged = a.keys && a.stage_stride;
+    auto first_row = [&](int32_t b) {
+        return __builtin_amdgcn_readfirstlane(b * kRowsPerBlock + wid);
+    };
+    auto clamp_row = [&](int32_t r) { return r < n32 ? r : n32 - 1; };
+    int32_t blk = (int32_t)blockIdx.x;
+    int32_t r0 = first_row(blk);
+    Buf bufA, bufB;
+    load_row(bufA, clamp_row(r0));
+    for (; blk < nblk; blk += (int32_t)gridDim.x) {
+        const int32_t base = blk * kRowsPerBlock;
+        for (int32_t j = 0; j < per_wave; j += 2) {
+            const int32_t r1 = r0 + a.waves;
+            load_row(bufB, clamp_row(r1));
+            if (r0 < n32)
+                process_row(bufA, r0, r0 - base);
+            const int32_t r2 = j + 2 < per_wave ? r1 + a.waves : first_row(blk + (int32_t)gridDim.x);
+            load_row(bufA, clamp_row(r2));
+            if (r1 < n32)
+                process_row(bufB, r1, r1 - base);
+            r0 = r2;
+        }
+        if (staged) {
+            __syncthreads();
+            const int32_t total = a.L * kRowsPerBlock;
+            for (int32_t q = tid; q < total; q += (int32_t)blockDim.x) {
+                const int32_t t = q / kRowsPerBlock, i = q % kRowsPerBlock;
+                if (base + i < n32)
+                    a.keys[(int64_t)t * a.key_ld + base + i] =
+                        *(const lds_u64 *)(size_t)stage_addr(a, t, i);
             }
-        } else {
-            Buf buf;
-            for (int rr = 0; rr < nrows; ++rr) {
-                load_row(buf, row0 + rr);
-                process_row(buf, row0 + rr, rr, nrows, row0);
-            }
+            __syncthreads();
         }
     }
 
@@ -690,7 +973,7 @@ hipError_t launch_one(const HashArgs &a, int block, size_t lds, hipStream_t st, 
         return e;
     if (per_cu < 1)
         return hipErrorInvalidConfiguration;
-    int64_t want = (nblk + a.waves - 1) / a.waves;
+    int64_t want = nblk; // one block of RB rows per workgroup step
     int64_t cap = (int64_t)device_cu_count() * per_cu;
     int grid = (int)(want < cap ? want : cap);
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, st, a);
@@ -810,6 +1093,8 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         LSH_FAIL(LSH_EINVAL, "key_ld %lld < n %lld", (long long)key_ld, (long long)pts->n);
     if (pts->n == 0)
         return LSH_OK;
+    if (pts->n >= ((int64_t)1 << 30))
+        LSH_FAIL(LSH_EINVAL, "n = %lld points: hash at most 2^30 - 1 per call", (long long)pts->n);
 
     a.x = pts->x;
     a.ld = pts->ld;
@@ -849,19 +1134,70 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         LSH_FAIL(LSH_EINVAL, "d = %d exceeds the single-pass row size (%d elements%s)", pts->d,
                  64 * 32 * (al ? per16 : 1), al ? "" : "; rows are not 16-byte aligned");
 
-    // LDS layout
-    a.tab_bytes = align16(pts->d * 2);
-    a.mpad = (int32_t)align_up((size_t)bin_pos(a.m), 256);
-    size_t shared = (size_t)a.tab_bytes + align16(bin_pos(a.m) * 4) + align16(a.L * 16);
-    size_t per_wave = (size_t)a.mpad * 4 + (size_t)a.L * kRowsPerBlock * 8 +
-                      align16(((a.m + 63) / 64) * 8);
-    a.wave_bytes = (int32_t)align_up(per_wave, 16);
+    // LDS layout: per-wave regions of a power-of-two size (so a slot's
+    // address is offset | region base), then the shared table and constants
+    a.mpad = (int32_t)align_up((size_t)bin_pos(a.m) + kTrashSlots, 4);
+    int region = 256;
+    while (region < a.mpad * 4)
+        region <<= 1;
+    a.wave_region = region;
+    const int vec = al ? per16 : 1;
+    a.tab_entries = 64 * ch * vec;
     const size_t lds_max = 160 * 1024;
     const int64_t nblk = (pts->n + kRowsPerBlock - 1) / kRowsPerBlock;
+    const size_t masks = (size_t)((a.m + 63) / 64) * 8;
+    // key staging: ceil(L / waves) tables (rounded up to a power of two) per
+    // chunk of RB + 1 keys each, chunk c in the unused tail of wave c's
+    // region when it fits there, else in an area of its own
+    bool stage_on = out->keys != nullptr;
+    auto stage_for = [&](int wv, size_t area_off) -> size_t {
+        a.stage_base = a.stage_stride = a.stage_tpc_log2 = 0;
+        if (!stage_on)
+            return 0;
+        int lg = 0;
+        while ((1 << lg) * wv < a.L)
+            ++lg;
+        const size_t chunk = (size_t)(1 << lg) * (kRowsPerBlock + 1) * 8;
+        const size_t nchunk = (size_t)((a.L + (1 << lg) - 1) >> lg);
+        a.stage_tpc_log2 = lg;
+        if ((size_t)region - (size_t)a.mpad * 4 >= chunk) {
+            a.stage_base = a.mpad * 4;
+            a.stage_stride = region;
+            return 0;
+        }
+        a.stage_base = (int32_t)area_off;
+        a.stage_stride = (int32_t)chunk;
+        return nchunk * chunk;
+    };
+    auto lds_for = [&](int wv) {
+        size_t off = (size_t)wv * region;
+        size_t tab = off;
+        off += align_up((size_t)a.tab_entries * 4, 16);
+        size_t blo = off;
+        off += align_up((size_t)bin_pos(a.m) * 4, 16);
+        size_t hio = off;
+        off += align_up((size_t)a.L * 16, 16);
+        size_t mo = off;
+        off += (size_t)wv * masks;
+        off = align_up(off, 16);
+        off += stage_for(wv, off);
+        a.tab_off = (int32_t)tab;
+        a.bl_off = (int32_t)blo;
+        a.hinit_off = (int32_t)hio;
+        a.mask_off = (int32_t)mo;
+        return off;
+    };
+    // more waves per workgroup amortise the table; fewer fit more workgroups
     int waves = 8;
-    while (waves > 1 && (shared + (size_t)waves * a.wave_bytes > lds_max || waves > nblk))
+    while (waves > 1 && (lds_for(waves) > lds_max || waves > nblk))
         waves >>= 1;
-    size_t lds = shared + (size_t)waves * a.wave_bytes;
+    if (lds_for(waves) > lds_max && stage_on) {
+        stage_on = false; // keys too many to stage: store them directly
+        waves = 8;
+        while (waves > 1 && (lds_for(waves) > lds_max || waves > nblk))
+            waves >>= 1;
+    }
+    size_t lds = lds_for(waves);
     if (lds > lds_max)
         LSH_FAIL(LSH_EINVAL, "d=%d, m=%d, L=%d need %zu bytes of LDS (max %zu)", pts->d, a.m, a.L,
                  lds, lds_max);

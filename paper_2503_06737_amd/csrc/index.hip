@@ -23,9 +23,9 @@
 
 namespace lsh {
 
-constexpr int kSortThreads = 512;
+constexpr int kSortThreads = 1024;
 constexpr int kSortItems = 8;
-constexpr int kSortTile = kSortThreads * kSortItems; // 4096 keys per tile
+constexpr int kSortTile = kSortThreads * kSortItems; // 8192 keys per tile
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kPasses = 8;
 constexpr int kRadix = 256;
@@ -91,19 +91,24 @@ __global__ __launch_bounds__(kSortThreads) void sort_hist_kernel(SortArgs a)
 
 // ------------------------------------------------------------------ plan
 
-__global__ void sort_plan_kernel(SortArgs a)
+__global__ __launch_bounds__(kRadix) void sort_plan_kernel(SortArgs a)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.L)
-        return;
+    const int t = blockIdx.x;
     const uint32_t *g = a.ghist + (int64_t)t * kPasses * kRadix;
+    __shared__ int s_trivial[kPasses];
+    if (threadIdx.x < kPasses)
+        s_trivial[threadIdx.x] = 0;
+    __syncthreads();
+    for (int p = 0; p < kPasses; ++p)
+        if ((int64_t)g[p * kRadix + threadIdx.x] == a.n)
+            s_trivial[p] = 1; // one digit value holds every key: identity pass
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
     bool active[kPasses];
     int P = 0;
     for (int p = 0; p < kPasses; ++p) {
-        bool trivial = false;
-        for (int d = 0; d < kRadix; ++d)
-            trivial |= (int64_t)g[p * kRadix + d] == a.n;
-        active[p] = !trivial;
+        active[p] = !s_trivial[p];
         P += active[p];
     }
     if (P == 0) { // every key equal: one pass still copies keys and ids out
@@ -381,43 +386,48 @@ __global__ __launch_bounds__(1024) void head_scan_kernel(HeadArgs a)
 
 __global__ __launch_bounds__(kHeadThreads) void head_write_kernel(HeadArgs a)
 {
+    constexpr int kW = kHeadThreads / kWave;
+    __shared__ uint32_t pre[kHeadItems][kW];
     const int t = blockIdx.y;
     const uint64_t *k = a.sk + (int64_t)t * a.n;
     const int64_t base = (int64_t)blockIdx.x * kHeadTile;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-    // thread owns kHeadItems consecutive positions
-    const int64_t i0 = base + (int64_t)tid * kHeadItems;
-    uint32_t flags = 0, cnt = 0;
+    // item it of thread tid is position base + it*256 + tid: tile order is (it, wave, lane)
+    uint64_t bal[kHeadItems];
+    uint64_t key[kHeadItems];
+#pragma unroll
     for (int it = 0; it < kHeadItems; ++it) {
-        int64_t i = i0 + it;
-        if (i < a.n && is_head(k, i)) {
-            flags |= 1u << it;
-            ++cnt;
+        int64_t i = base + it * kHeadThreads + tid;
+        bool h = false;
+        key[it] = 0;
+        if (i < a.n) {
+            key[it] = k[i];
+            h = i == 0 || key[it] != k[i - 1];
         }
+        bal[it] = __ballot(h);
+        if (lane == 0)
+            pre[it][wid] = __popcll(bal[it]);
     }
-    // block exclusive scan of cnt
-    uint32_t incl = cnt;
-    for (int o = 1; o < kWave; o <<= 1) {
-        uint32_t v = __shfl_up(incl, o, kWave);
-        if (lane >= o)
-            incl += v;
-    }
-    __shared__ uint32_t wsum[kHeadThreads / kWave];
-    if (lane == kWave - 1)
-        wsum[wid] = incl;
     __syncthreads();
-    uint32_t woff = 0;
-    for (int w = 0; w < wid; ++w)
-        woff += wsum[w];
-    uint32_t u = a.tile_cnt[(int64_t)t * a.ntiles + blockIdx.x] + woff + incl - cnt;
+    if (tid == 0) {
+        uint32_t run = a.tile_cnt[(int64_t)t * a.ntiles + blockIdx.x];
+        for (int it = 0; it < kHeadItems; ++it)
+            for (int w = 0; w < kW; ++w) {
+                uint32_t c = pre[it][w];
+                pre[it][w] = run;
+                run += c;
+            }
+    }
+    __syncthreads();
     uint64_t *uk = a.ukeys + (int64_t)t * a.n;
     uint32_t *of = a.offs + (int64_t)t * (a.n + 1);
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
     for (int it = 0; it < kHeadItems; ++it) {
-        if (flags & (1u << it)) {
-            int64_t i = i0 + it;
-            uk[u] = k[i];
-            of[u] = (uint32_t)i;
-            ++u;
+        if ((bal[it] >> lane) & 1ull) {
+            uint32_t u = pre[it][wid] + __popcll(bal[it] & lt);
+            uk[u] = key[it];
+            of[u] = (uint32_t)(base + it * kHeadThreads + tid);
         }
     }
 }
@@ -568,7 +578,7 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
         return fail("hipMemsetAsync", e);
     dim3 tiles(wl.ntiles, L);
     hipLaunchKernelGGL(sort_hist_kernel, tiles, dim3(kSortThreads), 0, s, sa);
-    hipLaunchKernelGGL(sort_plan_kernel, dim3((L + 63) / 64), dim3(64), 0, s, sa);
+    hipLaunchKernelGGL(sort_plan_kernel, dim3(L), dim3(kRadix), 0, s, sa);
     for (int p = 0; p < kPasses; ++p) {
         hipLaunchKernelGGL(sort_upsweep_kernel, tiles, dim3(kSortThreads), 0, s, sa, p);
         hipLaunchKernelGGL(sort_scan_kernel, dim3(L), dim3(kRadix), 0, s, sa, p);
