@@ -1,312 +1,918 @@
 // Index construction on gfx950 (Section 3.1: store every point in the
 // bucket of its key, one table per group of K components).
 //
-// Per table, the (key, id) pairs are put in (key, id) order by a stable
-// least-significant-digit radix sort over the 64-bit key, 8 bits per pass:
-//   hist   - one read of all keys: the 8 digit histograms of every table;
-//   plan   - per table, drop the passes whose digit is the same for every key
-//            (an identity permutation; SRP keys of K bits use ceil(K/8)
-//            passes) and route the remaining passes between two buffers so
-//            the last one lands in the index;
-//   upsweep/scan/downsweep per pass - tile digit counts, their exclusive scan
-//            over tiles (offset of each tile's run of each digit), and the
-//            stable scatter: inside a tile, each wave ranks its 64-key rows
-//            with 8 ballots per row (lanes holding the same digit), the ranks
-//            are turned into tile positions through per-wave digit counters
-//            in LDS, the tile is reordered in LDS and written out as
-//            contiguous digit runs.
-// Then bucket boundaries: heads (key differs from its predecessor) are
-// counted per tile, scanned per table, and the distinct keys and the start
-// offset of every bucket are written.
+// The index of a table is its (key, id) pairs in (key, id) order plus the
+// run heads.  Keys are 64-bit digests (E2LSH) or K sign bits (SRP), so the
+// order is built most-significant-digit first:
+//   1. mask    - OR and AND of every key of a table: the bits that vary;
+//   2. msd     - the top B varying bits (B grows with n, at most 9) form the
+//                segment digit: per-tile digit counts, their scan (segment
+//                starts) and a stable scatter of (key, id) into 2^B segments
+//                per table;
+//   3. segment - one 512-thread workgroup per segment of at most 4096 keys
+//                sorts it in LDS: 16-bit index arrays ranked by the segment's
+//                varying 8-bit chunks, least significant first (only the top
+//                four when more vary, unless an adjacent pair shows two
+//                distinct keys that agree on them);
+//   4. big     - one 1024-thread workgroup per larger segment (heavy buckets,
+//                skewed digits) splits it recursively by its own top varying
+//                byte in global memory: parts holding a single key are
+//                copied, parts of at most 8192 keys are sorted in LDS;
+//   5. heads   - run heads are counted per tile, scanned per table, and the
+//                distinct keys and bucket start offsets are written.
+// Every scatter ranks keys stably (one ballot per digit bit gives the lanes
+// of a wave that share a digit), so ids stay ascending inside a bucket.
 
 #include "lsh_internal.h"
 
 namespace lsh {
 
-constexpr int kSortThreads = 1024;
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kSortThreads * kSortItems; // 8192 keys per tile
-constexpr int kSortWaves = kSortThreads / kWave;
-constexpr int kPasses = 8;
-constexpr int kRadix = 256;
+constexpr int kThreads = 1024;             // scatter / big-segment workgroups
+constexpr int kItems = 8;
+constexpr int kTile = kThreads * kItems;   // 8192 keys per scatter tile
+constexpr int kWaves = kThreads / kWave;
+constexpr int kMsdBitsMax = 9;
+constexpr int kMsdRadixMax = 1 << kMsdBitsMax;
+constexpr int kRadix = 256;                // 8-bit digits below the segment digit
+constexpr int kSegThreads = 512;
+constexpr int kSegSmall = kSegThreads * kItems; // 4096: segments sorted by kSegThreads
+constexpr int kSegLarge = kThreads * kItems;    // 8192: parts sorted inside the big path
+constexpr int kChunks = 8;     // 8-bit chunks of a key (a segment's varying bits lie below its digit)
+constexpr int kFastChunks = 4; // chunks sorted before the adjacent-pair check
+constexpr int kStackMax = 16 * kRadix; // pending parts of one big segment
 
 constexpr int kHeadThreads = 256;
 constexpr int kHeadItems = 16;
 constexpr int kHeadTile = kHeadThreads * kHeadItems;
 
-struct SortArgs {
+struct BuildArgs {
     const uint64_t *kin; // input keys [L][key_ld]
     int64_t key_ld;
     int64_t n;
     int32_t L;
     uint32_t id_base;
-    uint64_t *ka, *kb;   // key buffers [L][n]
-    uint32_t *ia, *ib;   // id buffers [L][n] (ia = index sorted_ids)
-    uint32_t *ghist;     // [L][8][256]
-    int32_t *plan;       // [L][8]: -1 skip, else src | dst << 2 (0 = input, 1 = A, 2 = B)
-    uint32_t *tile_hist; // [L][ntiles][256]
-    int32_t ntiles;
+    int32_t ntiles;       // scatter tiles per table
+    int32_t msd_bits;     // B
+    uint64_t *tor, *tand; // [L] OR / AND of the table's keys
+    uint32_t *tile_hist;  // [L][ntiles][2^B] digit counts -> global offsets
+    uint32_t *ghist;      // [L][2^B] segment sizes
+    uint32_t *seg_start;  // [L][2^B]
+    uint64_t *ka, *kb;    // key buffers [L][n]; kb ends sorted
+    uint32_t *ia, *ids;   // id buffers [L][n] (ids = the index's sorted_ids)
+    uint32_t *blist;      // [L * 2^B][2]: table, segment of the big segments
+    uint32_t *bcount;     // [2]: big segments, stack overflows (0 unless a bound fails)
+    uint32_t *stack;      // [grid][kStackMax][3]: start, size, buffer
 };
 
-__device__ __forceinline__ uint32_t digit_of(uint64_t k, int p) { return (uint32_t)(k >> (8 * p)) & 255u; }
-
-// ------------------------------------------------------------------ hist
-
-__global__ __launch_bounds__(kSortThreads) void sort_hist_kernel(SortArgs a)
+__device__ __forceinline__ int top_shift(uint64_t vm, int bits)
 {
-    __shared__ uint32_t h[kPasses][kRadix];
-    const int t = blockIdx.y;
-    for (int i = threadIdx.x; i < kPasses * kRadix; i += blockDim.x)
-        (&h[0][0])[i] = 0;
-    __syncthreads();
-    const uint64_t *k = a.kin + (int64_t)t * a.key_ld;
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortItems; ++it) {
-        int64_t i = base + it * kSortThreads + threadIdx.x;
-        const bool valid = i < a.n;
-        uint64_t key = valid ? k[i] : 0;
-        const uint64_t vmask = __ballot(valid);
+    if (!vm)
+        return 0;
+    const int hb = 63 - __clzll((long long)vm);
+    return hb >= bits ? hb - bits + 1 : 0;
+}
+
+__device__ __forceinline__ bool chunk_varies(uint64_t vm, int p)
+{
+    return ((vm >> (8 * p)) & 255u) != 0;
+}
+
+// Exclusive scan of v over threads [0, R) of the block (R <= blockDim.x);
+// every thread calls it.  wsum: LDS scratch of R / 64 words.
+__device__ __forceinline__ uint32_t scan_excl(uint32_t v, int R, uint32_t *wsum)
+{
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const uint32_t v0 = tid < R ? v : 0u;
+    uint32_t x = v0;
 #pragma unroll
-        for (int p = 0; p < kPasses; ++p) {
-            // a digit shared by every valid lane (common: the zero high bytes
-            // of SRP keys) is added once per wave instead of 64 times
-            uint32_t dg = digit_of(key, p);
-            uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
-            if ((__ballot(valid && dg == d0) == vmask) && vmask == ~0ull) {
-                if (lane_id() == 0)
-                    atomicAdd(&h[p][d0], 64u);
-            } else if (valid) {
-                atomicAdd(&h[p][dg], 1u);
-            }
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o)
+            x += y;
+    }
+    if (tid < R && (lane == kWave - 1 || tid == R - 1))
+        wsum[w] = x;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int q = 0; q < w && q * kWave < R; ++q)
+        pre += wsum[q];
+    __syncthreads();
+    return pre + x - v0;
+}
+
+// ------------------------------------------------------------------ init
+
+__global__ __launch_bounds__(256) void build_init_kernel(BuildArgs a)
+{
+    const int64_t nseg = (int64_t)a.L << a.msd_bits;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nseg;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        a.ghist[i] = 0;
+        if (i < a.L) {
+            a.tor[i] = 0;
+            a.tand[i] = ~0ull;
+        }
+        if (i < 2)
+            a.bcount[i] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ mask
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v |= __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_and64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v &= __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// f(i, keys[i]) for every i < cnt, split over the block with eight loads in
+// flight per thread (a single workgroup streams a whole part this way).
+template <typename F>
+__device__ __forceinline__ void for_each_key(const uint64_t *keys, uint32_t cnt, F f)
+{
+    const uint32_t nt = blockDim.x, tid = threadIdx.x;
+    for (uint32_t base = 0; base < cnt; base += 8 * nt) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = base + u * nt + tid;
+            v[u] = i < cnt ? keys[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = base + u * nt + tid;
+            if (i < cnt)
+                f(i, v[u]);
         }
     }
-    __syncthreads();
-    uint32_t *g = a.ghist + (int64_t)t * kPasses * kRadix;
-    for (int i = threadIdx.x; i < kPasses * kRadix; i += blockDim.x) {
-        uint32_t v = (&h[0][0])[i];
-        if (v)
-            atomicAdd(&g[i], v);
-    }
 }
 
-// ------------------------------------------------------------------ plan
-
-__global__ __launch_bounds__(kRadix) void sort_plan_kernel(SortArgs a)
+// OR / AND of keys[0, cnt) over the block (every thread calls; all get it).
+__device__ __forceinline__ void block_or_and(const uint64_t *keys, int64_t cnt, uint64_t *so,
+                                             uint64_t *sa, uint64_t &vo, uint64_t &va)
 {
-    const int t = blockIdx.x;
-    const uint32_t *g = a.ghist + (int64_t)t * kPasses * kRadix;
-    __shared__ int s_trivial[kPasses];
-    if (threadIdx.x < kPasses)
-        s_trivial[threadIdx.x] = 0;
+    vo = 0;
+    va = ~0ull;
+    for_each_key(keys, (uint32_t)cnt, [&](uint32_t, uint64_t v) {
+        vo |= v;
+        va &= v;
+    });
+    vo = wave_or64(vo);
+    va = wave_and64(va);
+    const int nw = blockDim.x / kWave, wid = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        so[wid] = vo;
+        sa[wid] = va;
+    }
     __syncthreads();
-    for (int p = 0; p < kPasses; ++p)
-        if ((int64_t)g[p * kRadix + threadIdx.x] == a.n)
-            s_trivial[p] = 1; // one digit value holds every key: identity pass
+    vo = 0;
+    va = ~0ull;
+    for (int w = 0; w < nw; ++w) {
+        vo |= so[w];
+        va &= sa[w];
+    }
     __syncthreads();
-    if (threadIdx.x != 0)
-        return;
-    bool active[kPasses];
-    int P = 0;
-    for (int p = 0; p < kPasses; ++p) {
-        active[p] = !s_trivial[p];
-        P += active[p];
-    }
-    if (P == 0) { // every key equal: one pass still copies keys and ids out
-        active[0] = true;
-        P = 1;
-    }
-    int i = 0, src = 0;
-    for (int p = 0; p < kPasses; ++p) {
-        if (!active[p]) {
-            a.plan[t * kPasses + p] = -1;
-            continue;
-        }
-        int dst = ((P - 1 - i) % 2 == 0) ? 1 : 2;
-        a.plan[t * kPasses + p] = src | (dst << 2);
-        src = dst;
-        ++i;
-    }
 }
 
-// --------------------------------------------------------------- upsweep
-
-__device__ __forceinline__ const uint64_t *src_keys(const SortArgs &a, int sel, int t)
-{
-    return sel == 0 ? a.kin + (int64_t)t * a.key_ld
-                    : (sel == 1 ? a.ka : a.kb) + (int64_t)t * a.n;
-}
-
-__global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortArgs a, int p)
+__global__ __launch_bounds__(kThreads) void mask_kernel(BuildArgs a)
 {
     const int t = blockIdx.y;
-    const int pl = a.plan[t * kPasses + p];
-    if (pl < 0)
-        return;
-    __shared__ uint32_t h[kRadix];
-    for (int i = threadIdx.x; i < kRadix; i += blockDim.x)
+    const uint64_t *k = a.kin + (int64_t)t * a.key_ld;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint64_t vo = 0, va = ~0ull;
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t i = base + it * kThreads + threadIdx.x;
+        if (i < a.n) {
+            const uint64_t v = k[i];
+            vo |= v;
+            va &= v;
+        }
+    }
+    vo = wave_or64(vo);
+    va = wave_and64(va);
+    __shared__ uint64_t so[kWaves], sa[kWaves];
+    const int wid = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        so[wid] = vo;
+        sa[wid] = va;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            so[0] |= so[w];
+            sa[0] &= sa[w];
+        }
+        atomicOr((unsigned long long *)&a.tor[t], (unsigned long long)so[0]);
+        atomicAnd((unsigned long long *)&a.tand[t], (unsigned long long)sa[0]);
+    }
+}
+
+// ------------------------------------------------------------ segment digit
+
+__global__ __launch_bounds__(kThreads) void msd_up_kernel(BuildArgs a)
+{
+    const int t = blockIdx.y;
+    const int R = 1 << a.msd_bits;
+    __shared__ uint32_t h[kMsdRadixMax];
+    for (int i = threadIdx.x; i < R; i += blockDim.x)
         h[i] = 0;
     __syncthreads();
-    const uint64_t *k = src_keys(a, pl & 3, t);
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortItems; ++it) {
-        int64_t i = base + it * kSortThreads + threadIdx.x;
+    const int shift = top_shift(a.tor[t] & ~a.tand[t], a.msd_bits);
+    const uint64_t *k = a.kin + (int64_t)t * a.key_ld;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t i = base + it * kThreads + threadIdx.x;
         if (i < a.n)
-            atomicAdd(&h[digit_of(k[i], p)], 1u);
+            atomicAdd(&h[(uint32_t)(k[i] >> shift) & (uint32_t)(R - 1)], 1u);
     }
     __syncthreads();
-    uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * kRadix;
-    for (int i = threadIdx.x; i < kRadix; i += blockDim.x)
+    uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
+    for (int i = threadIdx.x; i < R; i += blockDim.x) {
         th[i] = h[i];
+        if (h[i])
+            atomicAdd(&a.ghist[(t << a.msd_bits) + i], h[i]);
+    }
 }
 
-// ------------------------------------------------------------------ scan
-// tile_hist[t][tile][d] <- global start of tile's run of digit d.
-
-__global__ __launch_bounds__(kRadix) void sort_scan_kernel(SortArgs a, int p)
+// tile_hist[t][tile][d] <- global start of the tile's run of digit d;
+// seg_start[t][d] <- start of segment d.
+__global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
 {
     const int t = blockIdx.x;
-    if (a.plan[t * kPasses + p] < 0)
-        return;
-    __shared__ uint32_t s[kRadix];
+    const int R = 1 << a.msd_bits;
+    __shared__ uint32_t wsum[kMsdRadixMax / kWave];
     const int d = threadIdx.x;
-    // exclusive scan of the global digit counts
-    uint32_t c = a.ghist[((int64_t)t * kPasses + p) * kRadix + d];
-    s[d] = c;
-    __syncthreads();
-    for (int o = 1; o < kRadix; o <<= 1) {
-        uint32_t v = d >= o ? s[d - o] : 0;
-        __syncthreads();
-        s[d] += v;
-        __syncthreads();
-    }
-    uint32_t run = s[d] - c;
-    uint32_t *th = a.tile_hist + (int64_t)t * a.ntiles * kRadix + d;
-    int tile = 0;
-    for (; tile + 4 <= a.ntiles; tile += 4) {
-        uint32_t v0 = th[(tile + 0) * kRadix], v1 = th[(tile + 1) * kRadix];
-        uint32_t v2 = th[(tile + 2) * kRadix], v3 = th[(tile + 3) * kRadix];
-        th[(tile + 0) * kRadix] = run;
-        run += v0;
-        th[(tile + 1) * kRadix] = run;
-        run += v1;
-        th[(tile + 2) * kRadix] = run;
-        run += v2;
-        th[(tile + 3) * kRadix] = run;
-        run += v3;
-    }
-    for (; tile < a.ntiles; ++tile) {
-        uint32_t v = th[tile * kRadix];
-        th[tile * kRadix] = run;
+    const uint32_t c = d < R ? a.ghist[(t << a.msd_bits) + d] : 0u;
+    uint32_t run = scan_excl(c, R, wsum);
+    if (d >= R)
+        return;
+    a.seg_start[(t << a.msd_bits) + d] = run;
+    uint32_t *th = a.tile_hist + (int64_t)t * a.ntiles * R + d;
+    for (int tile = 0; tile < a.ntiles; ++tile) {
+        const uint32_t v = th[(int64_t)tile * R];
+        th[(int64_t)tile * R] = run;
         run += v;
     }
 }
 
-// ------------------------------------------------------------- downsweep
+// ------------------------------------------------------- stable tile scatter
 
-__global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(SortArgs a, int p)
+template <int RMAX> struct ScatterLds {
+    uint64_t key[kTile];
+    uint32_t id[kTile];
+    uint32_t whist[kWaves][RMAX];
+    uint32_t lbase[RMAX];
+    uint32_t wsum[RMAX / kWave];
+};
+
+// Stable scatter of one tile (1024 threads): keys (and ids, or id0 + i when
+// ids is NULL) [0, cnt) go to kout/iout at goff[digit] + (rank among the
+// tile's keys of that digit), digit = (key >> shift) & (2^bits - 1).  Wave w
+// ranks rows w*8 .. w*8+7 of 64 keys; the lanes holding the same digit come
+// from one ballot per digit bit.  The tile is reordered in LDS and written
+// as contiguous digit runs.  On return s.whist[0][d] holds the tile's count
+// of digit d.
+template <int RMAX>
+__device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t *kin,
+                                             const uint32_t *iin, uint32_t id0, int cnt,
+                                             int shift, int bits, const uint32_t *goff,
+                                             uint64_t *kout, uint32_t *iout)
 {
-    const int t = blockIdx.y;
-    const int pl = a.plan[t * kPasses + p];
-    if (pl < 0)
-        return;
-    const int src = pl & 3, dst = pl >> 2;
-
-    __shared__ uint64_t skey[kSortTile];
-    __shared__ uint32_t sid[kSortTile];
-    __shared__ uint32_t whist[kSortWaves][kRadix];
-    __shared__ uint32_t lbase[kRadix];
-    __shared__ uint32_t gbase[kRadix];
-
+    const int R = 1 << bits;
+    const uint32_t dmask = (uint32_t)R - 1u;
     const int tid = threadIdx.x, wid = tid / kWave, lane = lane_id();
-    for (int i = tid; i < kSortWaves * kRadix; i += blockDim.x)
-        (&whist[0][0])[i] = 0;
-    const uint32_t *toff = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * kRadix;
-    for (int i = tid; i < kRadix; i += blockDim.x)
-        gbase[i] = toff[i];
+    for (int i = tid; i < kWaves * RMAX; i += kThreads)
+        (&s.whist[0][0])[i] = 0;
     __syncthreads();
 
-    const uint64_t *kin = src_keys(a, src, t);
-    const uint32_t *iin = src == 0 ? nullptr : (src == 1 ? a.ia : a.ib) + (int64_t)t * a.n;
-    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
-    const int64_t wbase = tile0 + (int64_t)wid * (kWave * kSortItems);
-
-    uint64_t key[kSortItems];
-    uint32_t id[kSortItems];
-    uint32_t rank[kSortItems];
+    const int wbase = wid * (kWave * kItems);
+    uint64_t key[kItems];
+    uint32_t id[kItems], rank[kItems], dg[kItems];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        int64_t i = wbase + it * kWave + lane;
-        if (i < a.n) {
+    for (int it = 0; it < kItems; ++it) {
+        const int i = wbase + it * kWave + lane;
+        if (i < cnt) {
             key[it] = kin[i];
-            id[it] = iin ? iin[i] : a.id_base + (uint32_t)i;
+            id[it] = iin ? iin[i] : id0 + (uint32_t)i;
+            dg[it] = (uint32_t)(key[it] >> shift) & dmask;
         } else {
-            key[it] = ~0ull; // sorts last, never written out
+            // positions past the end rank after every real key of the last
+            // digit (they come last in the ranking order); never written
+            key[it] = 0;
             id[it] = 0xffffffffu;
+            dg[it] = dmask;
         }
     }
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        uint32_t dg = digit_of(key[it], p);
+    for (int it = 0; it < kItems; ++it) {
         uint64_t peers = ~0ull;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot((dg >> b) & 1u);
-            peers &= ((dg >> b) & 1u) ? bal : ~bal;
+        for (int b = 0; b < bits; ++b) {
+            const uint64_t bal = __ballot((dg[it] >> b) & 1u);
+            peers &= ((dg[it] >> b) & 1u) ? bal : ~bal;
         }
-        uint32_t before = __popcll(peers & lt);
-        uint32_t old = whist[wid][dg];
+        const uint32_t before = __popcll(peers & lt);
+        const uint32_t old = s.whist[wid][dg[it]];
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (before == 0)
-            whist[wid][dg] = old + __popcll(peers);
+            s.whist[wid][dg[it]] = old + __popcll(peers);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         rank[it] = old + before;
     }
     __syncthreads();
-    // per digit: exclusive scan over waves, then over digits
-    if (tid < kRadix) {
-        uint32_t run = 0;
-        for (int w = 0; w < kSortWaves; ++w) {
-            uint32_t c = whist[w][tid];
-            whist[w][tid] = run;
-            run += c;
-        }
-        lbase[tid] = run;
-    }
-    __syncthreads();
-    // inclusive Hillis-Steele scan of the 256 digit totals (every thread
-    // reaches every barrier; threads >= 256 carry no data)
-    for (int o = 1; o < kRadix; o <<= 1) {
-        uint32_t u = (tid < kRadix && tid >= o) ? lbase[tid - o] : 0;
-        __syncthreads();
-        if (tid < kRadix)
-            lbase[tid] += u;
-        __syncthreads();
-    }
-    // lbase is now inclusive; exclusive base of digit d = lbase[d] - total(d)
+    // per digit: exclusive scan over waves; then over digits
+    uint32_t tot = 0;
+    if (tid < R) {
+        uint32_t c[kWaves];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        uint32_t dg = digit_of(key[it], p);
-        uint32_t excl = dg == 0 ? 0 : lbase[dg - 1];
-        uint32_t pos = excl + whist[wid][dg] + rank[it];
-        skey[pos] = key[it];
-        sid[pos] = id[it];
+        for (int w = 0; w < kWaves; ++w)
+            c[w] = s.whist[w][tid];
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            s.whist[w][tid] = tot;
+            tot += c[w];
+        }
+    }
+    const uint32_t excl = scan_excl(tot, R, s.wsum);
+    if (tid < R)
+        s.lbase[tid] = excl;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const uint32_t pos = s.lbase[dg[it]] + s.whist[wid][dg[it]] + rank[it];
+        s.key[pos] = key[it];
+        s.id[pos] = id[it];
     }
     __syncthreads();
-    uint64_t *kout = (dst == 1 ? a.ka : a.kb) + (int64_t)t * a.n;
-    uint32_t *iout = (dst == 1 ? a.ia : a.ib) + (int64_t)t * a.n;
-    for (int q = tid; q < kSortTile; q += kSortThreads) {
-        uint32_t idv = sid[q];
+    for (int q = tid; q < kTile; q += kThreads) {
+        const uint32_t idv = s.id[q];
         if (idv == 0xffffffffu)
             continue;
-        uint64_t k = skey[q];
-        uint32_t dg = digit_of(k, p);
-        uint32_t excl = dg == 0 ? 0 : lbase[dg - 1];
-        uint32_t g = gbase[dg] + (q - excl);
+        const uint64_t k = s.key[q];
+        const uint32_t d = (uint32_t)(k >> shift) & dmask;
+        const uint32_t g = goff[d] + ((uint32_t)q - s.lbase[d]);
         kout[g] = k;
         iout[g] = idv;
+    }
+    __syncthreads();
+    // tile digit counts for the caller (lbase is exclusive, so count = next - this)
+    if (tid < R) {
+        // the last digit also holds the padding, which ranks after its keys
+        const uint32_t nxt = tid + 1 < R ? s.lbase[tid + 1] : (uint32_t)cnt;
+        s.whist[0][tid] = nxt - s.lbase[tid];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void msd_scatter_kernel(BuildArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    ScatterLds<kMsdRadixMax> &s = *(ScatterLds<kMsdRadixMax> *)lds;
+    const int t = blockIdx.y;
+    const int R = 1 << a.msd_bits;
+    const int shift = top_shift(a.tor[t] & ~a.tand[t], a.msd_bits);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int cnt = (int)min((int64_t)kTile, a.n - base);
+    const uint32_t *goff = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
+    scatter_tile<kMsdRadixMax>(s, a.kin + (int64_t)t * a.key_ld + base, nullptr,
+                               a.id_base + (uint32_t)base, cnt, shift, a.msd_bits, goff,
+                               a.ka + (int64_t)t * a.n, a.ia + (int64_t)t * a.n);
+}
+
+// ------------------------------------------------- segment sort in LDS
+
+template <int NT> struct SegLds {
+    static constexpr int S = NT * kItems;
+    uint64_t key[S];
+    uint32_t id[S];
+    uint16_t ix[2][S];
+    uint32_t whist[NT / kWave][kRadix];
+    uint32_t lbase[kRadix];
+    uint32_t wsum[kRadix / kWave];
+    uint64_t so[NT / kWave], sa[NT / kWave];
+    int flag;
+};
+
+// One stable counting pass of the index array src -> dst by chunk p of the
+// keys.  Wave w ranks positions [w*rows*64, (w+1)*rows*64), row by row.
+template <int NT>
+__device__ __forceinline__ void seg_rank_pass(SegLds<NT> &s, const uint16_t *src, uint16_t *dst,
+                                              int cnt, int rows, int p)
+{
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, wid = tid / kWave, lane = lane_id();
+    for (int i = tid; i < NW * kRadix; i += NT)
+        (&s.whist[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    uint32_t dgs[kItems], rank[kItems];
+    uint16_t ixs[kItems];
+    const int wbase = wid * rows * kWave;
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        if (it < rows) {
+            const int j = wbase + it * kWave + lane;
+            const bool valid = j < cnt;
+            const uint16_t ix = valid ? src[j] : 0;
+            // positions past the end take digit 255 and rank after every
+            // real key (they come last in the ranking order); never stored
+            const uint32_t dg = valid ? (uint32_t)(s.key[ix] >> (8 * p)) & 255u : 255u;
+            uint64_t peers = ~0ull;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t bal = __ballot((dg >> b) & 1u);
+                peers &= ((dg >> b) & 1u) ? bal : ~bal;
+            }
+            const uint32_t before = __popcll(peers & lt);
+            const uint32_t old = s.whist[wid][dg];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (before == 0)
+                s.whist[wid][dg] = old + __popcll(peers);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            rank[it] = old + before;
+            dgs[it] = dg;
+            ixs[it] = ix;
+        }
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    if (tid < kRadix) {
+        uint32_t c[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            c[w] = s.whist[w][tid];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            s.whist[w][tid] = tot;
+            tot += c[w];
+        }
+    }
+    const uint32_t excl = scan_excl(tot, kRadix, s.wsum);
+    if (tid < kRadix)
+        s.lbase[tid] = excl;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        if (it < rows) {
+            const int j = wbase + it * kWave + lane;
+            if (j < cnt)
+                dst[s.lbase[dgs[it]] + s.whist[wid][dgs[it]] + rank[it]] = ixs[it];
+        }
+    }
+    __syncthreads();
+}
+
+// Sorts the keys [0, cnt) (cnt <= NT * 8) of kin / iin by (key, id) -- ids
+// ascend on entry, every pass is stable -- and writes them to kout / iout
+// (which may alias kin / iin: everything is read before anything is written).
+template <int NT>
+__device__ void seg_sort_body(SegLds<NT> &s, const uint64_t *kin, const uint32_t *iin, int cnt,
+                              uint64_t *kout, uint32_t *iout)
+{
+    const int tid = threadIdx.x;
+    uint64_t vo = 0, va = ~0ull;
+    {
+        uint64_t kv[kItems];
+        uint32_t iv[kItems];
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+            const int j = u * NT + tid;
+            kv[u] = j < cnt ? kin[j] : 0;
+            iv[u] = j < cnt ? iin[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+            const int j = u * NT + tid;
+            if (j < cnt) {
+                s.key[j] = kv[u];
+                s.id[j] = iv[u];
+                s.ix[0][j] = (uint16_t)j;
+                vo |= kv[u];
+                va &= kv[u];
+            }
+        }
+    }
+    vo = wave_or64(vo);
+    va = wave_and64(va);
+    if (lane_id() == 0) {
+        s.so[tid / kWave] = vo;
+        s.sa[tid / kWave] = va;
+    }
+    if (tid == 0)
+        s.flag = 0;
+    __syncthreads();
+    vo = 0;
+    va = ~0ull;
+    for (int w = 0; w < NT / kWave; ++w) {
+        vo |= s.so[w];
+        va &= s.sa[w];
+    }
+    const uint64_t vm = vo & ~va;
+    uint32_t all = 0; // bit p: chunk p varies inside the segment
+    for (int p = 0; p < kChunks; ++p)
+        all |= chunk_varies(vm, p) ? 1u << p : 0u;
+    uint32_t fast = all; // the top kFastChunks of them
+    for (int c = __popc(all) - kFastChunks; c > 0; --c)
+        fast &= fast - 1;
+    const int rows = (cnt + NT - 1) / NT;
+
+    int cur = 0;
+    for (int p = 0; p < kChunks; ++p) {
+        if ((fast >> p) & 1u) {
+            seg_rank_pass<NT>(s, s.ix[cur], s.ix[cur ^ 1], cnt, rows, p);
+            cur ^= 1;
+        }
+    }
+    if (fast != all) {
+        // distinct keys that agree on the sorted chunks would be out of order
+        uint64_t lo = 0;
+        for (int p = 0; p < kChunks; ++p)
+            if (((all & ~fast) >> p) & 1u)
+                lo |= 0xffull << (8 * p);
+        for (int j = tid + 1; j < cnt; j += NT) {
+            const uint64_t x = s.key[s.ix[cur][j]], y = s.key[s.ix[cur][j - 1]];
+            if (x != y && ((x ^ y) & ~lo) == 0)
+                s.flag = 1;
+        }
+        __syncthreads();
+        if (s.flag) {
+            for (int j = tid; j < cnt; j += NT)
+                s.ix[0][j] = (uint16_t)j;
+            __syncthreads();
+            cur = 0;
+            for (int p = 0; p < kChunks; ++p) {
+                if ((all >> p) & 1u) {
+                    seg_rank_pass<NT>(s, s.ix[cur], s.ix[cur ^ 1], cnt, rows, p);
+                    cur ^= 1;
+                }
+            }
+        }
+    }
+    for (int j = tid; j < cnt; j += NT) {
+        const uint16_t ix = s.ix[cur][j];
+        kout[j] = s.key[ix];
+        iout[j] = s.id[ix];
+    }
+    __syncthreads();
+}
+
+// Segment d of table t (blockIdx = (d, t)) when it holds 1..kSegSmall keys.
+__global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(BuildArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    SegLds<kSegThreads> &s = *(SegLds<kSegThreads> *)lds;
+    const int d = blockIdx.x, t = blockIdx.y;
+    if (d >= (1 << a.msd_bits))
+        return;
+    const int e = (t << a.msd_bits) + d;
+    const int cnt = (int)a.ghist[e];
+    if (cnt == 0 || cnt > kSegSmall)
+        return;
+    const int64_t base = (int64_t)t * a.n + a.seg_start[e];
+    seg_sort_body<kSegThreads>(s, a.ka + base, a.ia + base, cnt, a.kb + base, a.ids + base);
+}
+
+// --------------------------------------------------------- big segments
+
+// One workgroup lists the segments larger than kSegSmall.
+__global__ __launch_bounds__(kThreads) void big_plan_kernel(BuildArgs a)
+{
+    __shared__ uint32_t part[kThreads];
+    const int tid = threadIdx.x;
+    const int nseg = a.L << a.msd_bits;
+    const int per = (nseg + kThreads - 1) / kThreads;
+    const int lo = tid * per, hi = min(nseg, lo + per);
+    uint32_t nb = 0;
+    for (int e = lo; e < hi; ++e)
+        nb += a.ghist[e] > (uint32_t)kSegSmall;
+    part[tid] = nb;
+    __syncthreads();
+    for (int o = 1; o < kThreads; o <<= 1) {
+        const uint32_t u = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += u;
+        __syncthreads();
+    }
+    uint32_t bi = part[tid] - nb;
+    for (int e = lo; e < hi; ++e) {
+        if (a.ghist[e] > (uint32_t)kSegSmall) {
+            a.blist[2 * bi] = (uint32_t)(e >> a.msd_bits);
+            a.blist[2 * bi + 1] = (uint32_t)(e & ((1 << a.msd_bits) - 1));
+            ++bi;
+        }
+    }
+    if (tid == kThreads - 1)
+        a.bcount[0] = part[tid];
+}
+
+struct BigLds {
+    union {
+        ScatterLds<kRadix> sc;
+        SegLds<kThreads> sg;
+    } u;
+    uint32_t hist[kRadix];
+    uint32_t run[kRadix];
+    uint32_t wsum[kRadix / kWave];
+    uint64_t so[kWaves], sa[kWaves];
+    uint32_t cls[kWaves][4]; // per-wave class counts of the 3-way partition
+    uint64_t pivot;
+    uint32_t pivot_cnt;
+    int top;
+};
+
+// Stable 3-way partition of keys [0, cnt) around pivot: class 0 (key <
+// pivot), 1 (==), 2 (>) go to kout/iout at base[class] + (rank among the
+// part's keys of that class).  Tiles of 8192 keys in order; wave w ranks
+// rows w*8 .. w*8+7 of 64 keys with two ballots; base[] advances per tile.
+__device__ __noinline__ void partition3(BigLds &s, const uint64_t *kin, const uint32_t *iin, uint32_t cnt,
+                           uint64_t pivot, uint32_t *base, uint64_t *kout, uint32_t *iout)
+{
+    const int tid = threadIdx.x, wid = tid / kWave, lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t t0 = 0; t0 < cnt; t0 += kTile) {
+        uint32_t cls[kItems], rank[kItems];
+        uint32_t r0 = 0, r1 = 0, r2 = 0; // this wave's running class counts
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
+            uint32_t c = 3;
+            if (i < cnt) {
+                const uint64_t k = kin[i];
+                c = k < pivot ? 0u : (k == pivot ? 1u : 2u);
+            }
+            const uint64_t b0 = __ballot(c == 0), b1 = __ballot(c == 1), b2 = __ballot(c == 2);
+            const uint64_t mine = c == 0 ? b0 : (c == 1 ? b1 : b2);
+            rank[it] = (c == 0 ? r0 : (c == 1 ? r1 : r2)) + __popcll(mine & lt);
+            r0 += __popcll(b0);
+            r1 += __popcll(b1);
+            r2 += __popcll(b2);
+            cls[it] = c;
+        }
+        if (lane == 0) {
+            s.cls[wid][0] = r0;
+            s.cls[wid][1] = r1;
+            s.cls[wid][2] = r2;
+        }
+        __syncthreads();
+        uint32_t p0 = 0, p1 = 0, p2 = 0; // class counts of the earlier waves
+        for (int w = 0; w < wid; ++w) {
+            p0 += s.cls[w][0];
+            p1 += s.cls[w][1];
+            p2 += s.cls[w][2];
+        }
+        const uint32_t q0 = base[0] + p0, q1 = base[1] + p1, q2 = base[2] + p2;
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t c = cls[it];
+            if (c < 3) {
+                const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
+                const uint32_t pos = (c == 0 ? q0 : (c == 1 ? q1 : q2)) + rank[it];
+                kout[pos] = kin[i];
+                iout[pos] = iin[i];
+            }
+        }
+        __syncthreads();
+        if (tid < 3) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kWaves; ++w)
+                tot += s.cls[w][tid];
+            base[tid] += tot;
+        }
+        __syncthreads();
+    }
+}
+
+// The big path calls these out of line: inlined together with the
+// partition they exceed the register budget of a 1024-thread workgroup.
+__device__ __noinline__ void big_seg_sort(SegLds<kThreads> &s, const uint64_t *kin,
+                                          const uint32_t *iin, int cnt, uint64_t *kout,
+                                          uint32_t *iout)
+{
+    seg_sort_body<kThreads>(s, kin, iin, cnt, kout, iout);
+}
+
+__device__ __noinline__ void big_scatter(ScatterLds<kRadix> &s, const uint64_t *kin,
+                                         const uint32_t *iin, int cnt, int shift,
+                                         const uint32_t *goff, uint64_t *kout, uint32_t *iout)
+{
+    scatter_tile<kRadix>(s, kin, iin, 0, cnt, shift, 8, goff, kout, iout);
+}
+
+// One workgroup per big segment: a stack of parts (start within the table,
+// size, buffer 0 = ka/ia, 1 = kb/ids).  A part with one key is moved to
+// kb/ids as it is; a part of at most kSegLarge keys is sorted in LDS into
+// kb/ids; a larger one is split by its top 8 varying bits into the other
+// buffer (a stable scatter, tile by tile in order) and its non-empty
+// children are pushed.  Before that, a key filling at least 16 of 64 evenly
+// spaced samples is split off by a stable 3-way partition (its run is final;
+// the smaller and larger keys are pushed).  A segment varies in at most bits
+// 0..62 and each split removes at least 8 varying bits, so a path holds at
+// most 8 splits (255 pushes each) plus partitions (2 each, every one taking
+// the sampled key's run out of the part), far below kStackMax.
+__global__ __launch_bounds__(kThreads) void big_sort_kernel(BuildArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    BigLds &s = *(BigLds *)lds;
+    const int tid = threadIdx.x;
+    const uint32_t nb = a.bcount[0];
+    uint32_t *stk = a.stack + (size_t)blockIdx.x * kStackMax * 3;
+    for (uint32_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+        const int t = (int)a.blist[2 * bi];
+        const int e = (t << a.msd_bits) + (int)a.blist[2 * bi + 1];
+        const int64_t tb = (int64_t)t * a.n;
+        if (tid == 0) {
+            stk[0] = a.seg_start[e];
+            stk[1] = a.ghist[e];
+            stk[2] = 0;
+            s.top = 1;
+        }
+        __syncthreads();
+        while (true) {
+            const int top = s.top;
+            if (top == 0)
+                break;
+            const uint32_t start = stk[3 * (top - 1)];
+            const uint32_t size = stk[3 * (top - 1) + 1];
+            const uint32_t buf = stk[3 * (top - 1) + 2];
+            __syncthreads();
+            if (tid == 0)
+                s.top = top - 1;
+            const uint64_t *kin = (buf ? a.kb : a.ka) + tb + start;
+            const uint32_t *iin = (buf ? a.ids : a.ia) + tb + start;
+            uint64_t *kout = a.kb + tb + start;
+            uint32_t *iout = a.ids + tb + start;
+            if (size <= (uint32_t)kSegLarge) {
+                big_seg_sort(s.u.sg, kin, iin, (int)size, kout, iout);
+                continue;
+            }
+            // a key that fills at least a quarter of 64 evenly spaced samples
+            // is split off by a stable 3-way partition: its run is final
+            if (tid < kWave) {
+                const uint64_t ks = kin[(uint64_t)tid * size / kWave];
+                uint32_t c = 0;
+                for (int j = 0; j < kWave; ++j) {
+                    const uint64_t kj = ((uint64_t)(uint32_t)__shfl((int)(ks >> 32), j, kWave) << 32) |
+                                        (uint32_t)__shfl((int)(uint32_t)ks, j, kWave);
+                    c += kj == ks;
+                }
+                // largest count, lowest lane on ties
+                uint32_t best = (c << 8) | (uint32_t)(kWave - 1 - tid);
+                for (int o = 32; o >= 1; o >>= 1)
+                    best = max(best, (uint32_t)__shfl_xor((int)best, o, kWave));
+                if ((uint32_t)(kWave - 1 - tid) == (best & 255u)) {
+                    s.pivot = ks;
+                    s.pivot_cnt = best >> 8;
+                }
+            }
+            __syncthreads();
+            if (s.pivot_cnt >= 16) {
+                const uint64_t pivot = s.pivot;
+                uint32_t nlt = 0, neq = 0;
+                for_each_key(kin, size, [&](uint32_t, uint64_t k) {
+                    nlt += k < pivot;
+                    neq += k == pivot;
+                });
+                nlt = wave_sum(nlt);
+                neq = wave_sum(neq);
+                if (lane_id() == 0) {
+                    s.cls[tid / kWave][0] = nlt;
+                    s.cls[tid / kWave][1] = neq;
+                }
+                __syncthreads();
+                nlt = neq = 0;
+                for (int w = 0; w < kWaves; ++w) {
+                    nlt += s.cls[w][0];
+                    neq += s.cls[w][1];
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    s.run[0] = 0;
+                    s.run[1] = nlt;
+                    s.run[2] = nlt + neq;
+                }
+                __syncthreads();
+                uint64_t *ko = (buf ? a.ka : a.kb) + tb + start;
+                uint32_t *io = (buf ? a.ia : a.ids) + tb + start;
+                partition3(s, kin, iin, size, pivot, s.run, ko, io);
+                if (tid == 0 && s.top + 3 > kStackMax) {
+                    atomicAdd(&a.bcount[1], 1u); // cannot happen (see the bound above)
+                } else if (tid == 0) {
+                    int tp = s.top;
+                    const uint32_t ngt = size - nlt - neq;
+                    if (nlt) {
+                        stk[3 * tp] = start;
+                        stk[3 * tp + 1] = nlt;
+                        stk[3 * tp + 2] = buf ^ 1u;
+                        ++tp;
+                    }
+                    if (buf) { // the equal run landed in ka / ia: one more move
+                        stk[3 * tp] = start + nlt;
+                        stk[3 * tp + 1] = neq;
+                        stk[3 * tp + 2] = 0;
+                        ++tp;
+                    }
+                    if (ngt) {
+                        stk[3 * tp] = start + nlt + neq;
+                        stk[3 * tp + 1] = ngt;
+                        stk[3 * tp + 2] = buf ^ 1u;
+                        ++tp;
+                    }
+                    s.top = tp;
+                }
+                __syncthreads();
+                continue;
+            }
+            uint64_t vo, va;
+            block_or_and(kin, size, s.so, s.sa, vo, va);
+            const uint64_t vm = vo & ~va;
+            if (vm == 0) { // one key: already in id order
+                if (buf == 0)
+                    for_each_key(kin, size, [&](uint32_t j, uint64_t k) {
+                        kout[j] = k;
+                        iout[j] = iin[j];
+                    });
+                __syncthreads();
+                continue;
+            }
+            const int shift = top_shift(vm, 8);
+            // digit counts of the whole part, then child starts
+            for (int i = tid; i < kRadix; i += kThreads)
+                s.hist[i] = 0;
+            __syncthreads();
+            for_each_key(kin, size, [&](uint32_t, uint64_t k) {
+                atomicAdd(&s.hist[(uint32_t)(k >> shift) & 255u], 1u);
+            });
+            __syncthreads();
+            const uint32_t c = tid < kRadix ? s.hist[tid] : 0u;
+            const uint32_t ex = scan_excl(c, kRadix, s.wsum);
+            if (tid < kRadix)
+                s.run[tid] = ex;
+            __syncthreads();
+            // push the children: runs of consecutive children of at most
+            // kSegLarge keys in total go as one part (sorting their union
+            // by key orders each of them: they are already grouped by
+            // digit), a larger child alone
+            if (tid == 0 && s.top + kRadix > kStackMax) {
+                atomicAdd(&a.bcount[1], 1u); // cannot happen (see the bound above)
+            } else if (tid == 0) {
+                int tp = s.top;
+                uint32_t bs = 0, bn = 0; // open batch: start, size
+                for (int d = 0; d <= kRadix; ++d) {
+                    const uint32_t cc = d < kRadix ? s.hist[d] : 0u;
+                    if (d < kRadix && cc == 0)
+                        continue;
+                    const bool big = cc > (uint32_t)kSegLarge;
+                    if (bn && (d == kRadix || big || bn + cc > (uint32_t)kSegLarge)) {
+                        stk[3 * tp] = start + bs;
+                        stk[3 * tp + 1] = bn;
+                        stk[3 * tp + 2] = buf ^ 1u;
+                        ++tp;
+                        bn = 0;
+                    }
+                    if (d == kRadix)
+                        break;
+                    if (big) {
+                        stk[3 * tp] = start + s.run[d];
+                        stk[3 * tp + 1] = cc;
+                        stk[3 * tp + 2] = buf ^ 1u;
+                        ++tp;
+                    } else {
+                        if (bn == 0)
+                            bs = s.run[d];
+                        bn += cc;
+                    }
+                }
+                s.top = tp;
+            }
+            __syncthreads();
+            // stable scatter into the other buffer, tile by tile in order
+            uint64_t *ko = (buf ? a.ka : a.kb) + tb + start;
+            uint32_t *io = (buf ? a.ia : a.ids) + tb + start;
+            for (uint32_t base = 0; base < size; base += kTile) {
+                const int cnt = (int)min((uint32_t)kTile, size - base);
+                big_scatter(s.u.sc, kin + base, iin + base, cnt, shift, s.run, ko, io);
+                if (tid < kRadix)
+                    s.run[tid] += s.u.sc.whist[0][tid];
+                __syncthreads();
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -432,6 +1038,15 @@ __global__ __launch_bounds__(kHeadThreads) void head_write_kernel(HeadArgs a)
     }
 }
 
+// Writes the index of an empty table set: nuniq = 0 and offs[t][0] = 0.
+__global__ __launch_bounds__(256) void empty_index_kernel(int64_t *nuniq, uint32_t *offs, int L)
+{
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < L; t += gridDim.x * blockDim.x) {
+        nuniq[t] = 0;
+        offs[t] = 0;
+    }
+}
+
 } // namespace lsh
 
 // ========================================================================
@@ -467,24 +1082,50 @@ IndexLayout index_layout(int64_t n, int32_t L)
 }
 
 struct WsLayout {
-    size_t ka, kb, ib, ghist, plan, tile_hist, tile_cnt, total;
-    int ntiles, nhtiles;
+    size_t ka, kb, ia, tor, tand, tile_hist, ghist, seg_start, blist, bcount, stack, tile_cnt,
+        total;
+    int ntiles, nhtiles, bits, big_grid;
 };
+
+// Segment digit width: about 2048 keys per segment, at most 2^9 segments.
+int msd_bits_for(int64_t n)
+{
+    int b = 1;
+    while (b < lsh::kMsdBitsMax && ((int64_t)2048 << b) < n)
+        ++b;
+    return b;
+}
 
 WsLayout ws_layout(int64_t n, int32_t L)
 {
     using lsh::align_up;
+    using namespace lsh;
     WsLayout w;
-    w.ntiles = (int)((n + lsh::kSortTile - 1) / lsh::kSortTile);
-    w.nhtiles = (int)((n + lsh::kHeadTile - 1) / lsh::kHeadTile);
-    w.ka = 0;
-    w.kb = w.ka + align_up((size_t)L * n * 8, 256);
-    w.ib = w.kb + align_up((size_t)L * n * 8, 256);
-    w.ghist = w.ib + align_up((size_t)L * n * 4, 256);
-    w.plan = w.ghist + align_up((size_t)L * lsh::kPasses * lsh::kRadix * 4, 256);
-    w.tile_hist = w.plan + align_up((size_t)L * lsh::kPasses * 4, 256);
-    w.tile_cnt = w.tile_hist + align_up((size_t)L * w.ntiles * lsh::kRadix * 4, 256);
-    w.total = w.tile_cnt + align_up((size_t)L * (w.nhtiles > 0 ? w.nhtiles : 1) * 4, 256);
+    w.ntiles = (int)((n + kTile - 1) / kTile);
+    w.nhtiles = (int)((n + kHeadTile - 1) / kHeadTile);
+    w.bits = msd_bits_for(n);
+    const size_t nseg = (size_t)L << w.bits;
+    // big segments: one workgroup per CU of an MI355X, each with its own stack
+    w.big_grid = (int)(nseg < 256 ? nseg : 256);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align_up(bytes ? bytes : 1, 256);
+        return at;
+    };
+    w.ka = take((size_t)L * n * 8);
+    w.kb = take((size_t)L * n * 8);
+    w.ia = take((size_t)L * n * 4);
+    w.tor = take((size_t)L * 8);
+    w.tand = take((size_t)L * 8);
+    w.tile_hist = take(((size_t)L * w.ntiles << w.bits) * 4);
+    w.ghist = take(nseg * 4);
+    w.seg_start = take(nseg * 4);
+    w.blist = take(nseg * 8);
+    w.bcount = take(16);
+    w.stack = take((size_t)w.big_grid * kStackMax * 12);
+    w.tile_cnt = take((size_t)L * (w.nhtiles > 0 ? w.nhtiles : 1) * 4);
+    w.total = o;
     return w;
 }
 
@@ -514,6 +1155,8 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     *out = nullptr;
     if (n < 0 || L < 1 || id_base < 0)
         LSH_FAIL(LSH_EINVAL, "bad n=%lld L=%d id_base=%lld", (long long)n, L, (long long)id_base);
+    if (L > 65536)
+        LSH_FAIL(LSH_EINVAL, "L = %d exceeds 65536 tables", L);
     if (key_ld == 0)
         key_ld = n;
     if (key_ld < n)
@@ -548,44 +1191,65 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
         return LSH_EHIP;
     };
     if (n == 0) {
-        hipError_t e = hipMemsetAsync(idx->nuniq, 0, (size_t)L * 8, s);
-        if (e == hipSuccess)
-            e = hipMemsetAsync(idx->offs, 0, (size_t)L * 4, s); // offs[t][0] = 0 (n+1 = 1)
+        hipLaunchKernelGGL(empty_index_kernel, dim3((L + 255) / 256), dim3(256), 0, s, idx->nuniq,
+                           idx->offs, L);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess)
-            return fail("hipMemsetAsync", e);
+            return fail("empty_index_kernel", e);
         *out = idx;
         return LSH_OK;
     }
 
     unsigned char *wb = (unsigned char *)ws;
-    SortArgs sa;
-    sa.kin = keys;
-    sa.key_ld = key_ld;
-    sa.n = n;
-    sa.L = L;
-    sa.id_base = (uint32_t)id_base;
-    sa.ka = (uint64_t *)(wb + wl.ka);
-    sa.kb = (uint64_t *)(wb + wl.kb);
-    sa.ia = idx->sorted_ids;
-    sa.ib = (uint32_t *)(wb + wl.ib);
-    sa.ghist = (uint32_t *)(wb + wl.ghist);
-    sa.plan = (int32_t *)(wb + wl.plan);
-    sa.tile_hist = (uint32_t *)(wb + wl.tile_hist);
-    sa.ntiles = wl.ntiles;
+    BuildArgs ba;
+    ba.kin = keys;
+    ba.key_ld = key_ld;
+    ba.n = n;
+    ba.L = L;
+    ba.id_base = (uint32_t)id_base;
+    ba.ntiles = wl.ntiles;
+    ba.msd_bits = wl.bits;
+    ba.tor = (uint64_t *)(wb + wl.tor);
+    ba.tand = (uint64_t *)(wb + wl.tand);
+    ba.tile_hist = (uint32_t *)(wb + wl.tile_hist);
+    ba.ghist = (uint32_t *)(wb + wl.ghist);
+    ba.seg_start = (uint32_t *)(wb + wl.seg_start);
+    ba.ka = (uint64_t *)(wb + wl.ka);
+    ba.kb = (uint64_t *)(wb + wl.kb);
+    ba.ia = (uint32_t *)(wb + wl.ia);
+    ba.ids = idx->sorted_ids;
+    ba.blist = (uint32_t *)(wb + wl.blist);
+    ba.bcount = (uint32_t *)(wb + wl.bcount);
+    ba.stack = (uint32_t *)(wb + wl.stack);
 
-    hipError_t e = hipMemsetAsync(sa.ghist, 0, (size_t)L * kPasses * kRadix * 4, s);
-    if (e != hipSuccess)
-        return fail("hipMemsetAsync", e);
+    const size_t scatter_lds = sizeof(ScatterLds<kMsdRadixMax>);
+    const size_t seg_lds = sizeof(SegLds<kSegThreads>);
+    const size_t big_lds = sizeof(BigLds);
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)msd_scatter_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)scatter_lds)) !=
+            hipSuccess ||
+        (e = hipFuncSetAttribute((const void *)seg_sort_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)seg_lds)) !=
+            hipSuccess ||
+        (e = hipFuncSetAttribute((const void *)big_sort_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)big_lds)) !=
+            hipSuccess)
+        return fail("hipFuncSetAttribute", e);
+
+    const int nseg = L << wl.bits;
     dim3 tiles(wl.ntiles, L);
-    hipLaunchKernelGGL(sort_hist_kernel, tiles, dim3(kSortThreads), 0, s, sa);
-    hipLaunchKernelGGL(sort_plan_kernel, dim3(L), dim3(kRadix), 0, s, sa);
-    for (int p = 0; p < kPasses; ++p) {
-        hipLaunchKernelGGL(sort_upsweep_kernel, tiles, dim3(kSortThreads), 0, s, sa, p);
-        hipLaunchKernelGGL(sort_scan_kernel, dim3(L), dim3(kRadix), 0, s, sa, p);
-        hipLaunchKernelGGL(sort_downsweep_kernel, tiles, dim3(kSortThreads), 0, s, sa, p);
-    }
+    hipLaunchKernelGGL(build_init_kernel, dim3((nseg + 255) / 256), dim3(256), 0, s, ba);
+    hipLaunchKernelGGL(mask_kernel, tiles, dim3(kThreads), 0, s, ba);
+    hipLaunchKernelGGL(msd_up_kernel, tiles, dim3(kThreads), 0, s, ba);
+    hipLaunchKernelGGL(msd_scan_kernel, dim3(L), dim3(kMsdRadixMax), 0, s, ba);
+    hipLaunchKernelGGL(msd_scatter_kernel, tiles, dim3(kThreads), scatter_lds, s, ba);
+    hipLaunchKernelGGL(seg_sort_kernel, dim3(1 << wl.bits, L), dim3(kSegThreads), seg_lds, s, ba);
+    hipLaunchKernelGGL(big_plan_kernel, dim3(1), dim3(kThreads), 0, s, ba);
+    hipLaunchKernelGGL(big_sort_kernel, dim3(wl.big_grid), dim3(kThreads), big_lds, s, ba);
+
     HeadArgs ha;
-    ha.sk = sa.ka;
+    ha.sk = ba.kb;
     ha.n = n;
     ha.L = L;
     ha.ntiles = wl.nhtiles;

@@ -83,3 +83,78 @@ def test_key_ld_strided_input():
     idx = lsh.lsh_build_index(t)
     sid = to_host(idx.arrays()[0], np.uint32)
     assert (sid == ref["sorted_ids"]).all()
+
+
+# ---- segments larger than one LDS sort (8192 keys) and the prefix check
+
+def test_heavy_bucket_spans_several_tiles():
+    """40% of a table share one key: its segment (top varying byte) exceeds the
+    LDS sort and is ordered by the segmented global pass; other tables mix
+    sizes so both parities of the pass count occur."""
+    g = _rng(6)
+    n = 40000
+    keys = g.integers(0, 2**63, (3, n), dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    heavy = g.random((3, n)) < 0.4
+    keys[0][heavy[0]] = np.uint64(0x8123456789ABCDEF)
+    # table 1: heavy key differs from its segment-mates only in the low 16 bits
+    keys[1][heavy[1]] = np.uint64(0x7700000000001234)
+    keys[1][::97] = np.uint64(0x7700000000000000) + g.integers(0, 1 << 16, keys[1][::97].size).astype(np.uint64)
+    # table 2: two heavy keys in the same top byte
+    keys[2][heavy[2]] = np.uint64(0x5500000000000001)
+    keys[2][heavy[2] & (g.random(n) < 0.5)] = np.uint64(0x55FF000000000001)
+    _check(keys, id_base=1000)
+
+
+def test_all_equal_large_and_segment_size_boundary():
+    n = 20000
+    keys = np.full((2, n), 0x0123456789ABCDEF, np.uint64)
+    # table 1: exactly 8192 keys in one segment, 8193 in another, rest spread
+    g = _rng(7)
+    k1 = g.integers(0, 2**63, n, dtype=np.int64).astype(np.uint64)
+    top = k1 >> np.uint64(56)
+    k1[top == 0x11] ^= np.uint64(0x0100000000000000)   # empty segments 0x11 and 0x22
+    k1[top == 0x22] ^= np.uint64(0x0100000000000000)
+    k1[:8192] = (k1[:8192] & np.uint64(0x00FFFFFFFFFFFFFF)) | np.uint64(0x1100000000000000)
+    k1[8192:8192 + 8193] = (k1[8192:8192 + 8193] & np.uint64(0x00FFFFFFFFFFFFFF)) | np.uint64(0x2200000000000000)
+    keys[1] = k1
+    _check(keys)
+
+
+def test_skewed_short_keys_big_segments():
+    """16-bit keys from a few values (clustered SRP codes): segments by the
+    high byte are far larger than 8192 and differ only in the low byte."""
+    g = _rng(8)
+    vals = g.integers(0, 1 << 16, 12).astype(np.uint64)
+    vals[1] = (vals[0] & np.uint64(0xFF00)) | np.uint64(0x3)
+    keys = vals[g.integers(0, vals.size, (4, 50000))]
+    _check(keys)
+
+
+def test_prefix_check_falls_back_to_every_chunk():
+    """Distinct keys that agree on bits 24..63 inside one small segment: the
+    four-chunk sort alone would leave them in id order, the adjacent-pair
+    check must trigger the full sort."""
+    g = _rng(9)
+    n = 6000
+    keys = g.integers(0, 2**63, (2, n), dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    for t in range(2):
+        src = g.integers(0, n, 800)
+        dst = g.integers(0, n, 800)
+        low = g.integers(1, 1 << 24, 800).astype(np.uint64)
+        keys[t, dst] = keys[t, src] ^ low              # siblings: same bits 24..63
+        keys[t, dst[:100]] = keys[t, src[:100]]        # and some exact duplicates
+    _check(keys)
+
+
+@pytest.mark.slow
+def test_sparse_image_rows_index_from_oracle_keys():
+    """Keys of the image-like workload (heavy all-zero-code bucket per table),
+    computed by the oracle, indexed on the GPU: every table bit-exact."""
+    from paper_2503_06737_amd import synth
+    wl = synth.C2
+    n, K, L = 120000, wl.K, 16
+    x = wl.points(n).astype(np.float64)
+    h, s = synth.cs_state(wl.d, K * L, wl.seed + 1)
+    b = synth.shifts(K * L, wl.w, wl.seed + 1)
+    keys = oracle.hash_points(x, oracle.E2LSH, K, L, kind="cs", w=wl.w, b=b, h=h, s=s)["keys"]
+    _check(keys)
