@@ -35,17 +35,22 @@ def _pipeline(x, Q, h, s, b, K, L, w, family, segs_split=None, watermark=None, k
     kw = dict(family=family, K=K, L=L, w=w, b=to_dev(b))
     keys = lsh.lsh_hash_cs(xd, to_dev(h), to_dev(s), recheck=True, **kw)["keys"]
     qkeys = lsh.lsh_hash_cs(Qd, to_dev(h), to_dev(s), recheck=True, **kw)["keys"]
+    # the oracle indexes and queries with its own keys; the rechecked GPU
+    # keys must equal them exactly
+    okw = dict(kind="cs", w=w, b=b, h=h, s=s)
+    rk = oracle.hash_points(x.astype(np.float64), family, K, L, **okw)["keys"]
+    rqk = oracle.hash_points(Q.astype(np.float64), family, K, L, **okw)["keys"]
+    assert (to_host(keys, np.uint64) == rk).all() and (to_host(qkeys, np.uint64) == rqk).all()
     splits = segs_split or [x.shape[0]]
     segs, ref_segs, lo = [], [], 0
-    kh = to_host(keys, np.uint64)
     for hi in splits:
         segs.append(lsh.lsh_build_index(keys[:, lo:hi].contiguous(), id_base=lo))
-        ref_segs.append(oracle.build_index(np.ascontiguousarray(kh[:, lo:hi]), lo))
+        ref_segs.append(oracle.build_index(np.ascontiguousarray(rk[:, lo:hi]), lo))
         lo = hi
     wm = x.shape[0] if watermark is None else watermark
     ids, sc, nc = lsh.lsh_query(segs, xd, Qd, qkeys, k=k, watermark=wm, metric=family)
-    rids, rsc, rnc = oracle.query(ref_segs, x.astype(np.float64), Q.astype(np.float64),
-                                  to_host(qkeys, np.uint64), k, wm, family)
+    rids, rsc, rnc = oracle.query(ref_segs, x.astype(np.float64), Q.astype(np.float64), rqk, k,
+                                  wm, family)
     return (ids, sc, nc), (rids, rsc, rnc)
 
 
@@ -105,6 +110,8 @@ def test_query_low_precision_base():
     idx = lsh.lsh_build_index(keys)
     ids, scv, nc = lsh.lsh_query([idx], to_dev(q), to_dev(Q), qkeys, k=10, metric=1,
                                  base_scale=to_dev(sc))
-    ref = oracle.query([oracle.build_index(to_host(keys, np.uint64))], x64, Q.astype(np.float64),
-                       to_host(qkeys, np.uint64), 10, 3000, 1)
+    rk = oracle.hash_points(x64, 1, 8, 8, kind="cs", h=h, s=s)["keys"]
+    rqk = oracle.hash_points(Q.astype(np.float64), 1, 8, 8, kind="cs", h=h, s=s)["keys"]
+    assert (to_host(keys, np.uint64) == rk).all() and (to_host(qkeys, np.uint64) == rqk).all()
+    ref = oracle.query([oracle.build_index(rk)], x64, Q.astype(np.float64), rqk, 10, 3000, 1)
     _compare(ids, scv, nc, *ref, what="bf16 base")

@@ -1,0 +1,91 @@
+"""Continuous-batching server: every query of a mixed query/insert stream
+against the oracle (one index over every point that arrived before it, the
+query's watermark), the same query run alone, segment merges, and the HBM
+budget."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_06737_amd import lsh, serve, synth
+from gpu_util import dev, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n0, d, K, L, w, family, seed):
+    x0 = synth.gaussian_clusters(n0, d, 8, 0.1, seed)
+    h, s = synth.cs_state(d, K * L, seed + 1)
+    b = synth.shifts(K * L, w, seed + 1)
+    qsrc = iter(synth.gaussian_clusters(4000, d, 8, 0.1, seed, stream=1))
+    isrc = iter(synth.gaussian_clusters(4000, d, 8, 0.1, seed, stream=2))
+    take = lambda it: (lambda m: np.stack([next(it) for _ in range(m)]))
+    return x0, h, s, b, take(qsrc), take(isrc)
+
+
+def _serve(n0=3000, d=64, K=8, L=8, w=8.0, family=lsh.E2LSH, n_req=60, max_points=40,
+           budget=60_000, seed=71, inflight=2, realtime=False):
+    dev()
+    x0, h, s, b, qsrc, isrc = _setup(n0, d, K, L, w, family, seed)
+    reqs = serve.poisson_stream(n_req, 1e4, 0.7, max_points, d, qsrc, isrc, seed)
+    srv = serve.Server(to_dev(x0), to_dev(h), to_dev(s), to_dev(b), K=K, L=L, w=w,
+                       capacity=n0 + sum(r.points.shape[0] for r in reqs), budget_bytes=budget,
+                       k=10, metric=family, max_inflight=inflight, recheck=True)
+    stats = srv.serve(reqs, realtime=realtime)
+    return srv, reqs, stats, (x0, h, s, b, K, L, w, family)
+
+
+def _check_oracle(srv, reqs, params):
+    x0, h, s, b, K, L, w, family = params
+    allx = np.concatenate([x0] + [r.points for r in reqs if r.kind == "insert"]).astype(np.float64)
+    okw = dict(kind="cs", w=w, b=b, h=h, s=s)
+    ref_idx = oracle.build_index(oracle.hash_points(allx, family, K, L, **okw)["keys"])
+    for r in reqs:
+        if r.kind != "query":
+            continue
+        q64 = r.points.astype(np.float64)
+        qk = oracle.hash_points(q64, family, K, L, **okw)["keys"]
+        rids, rsc, rnc = oracle.query([ref_idx], allx, q64, qk, 10, r.watermark, family)
+        assert (to_host(r.ncand) == rnc).all(), f"request at {r.arrival}: ncand"
+        np.testing.assert_allclose(to_host(r.score), rsc, rtol=1e-5, atol=1e-5)
+        ids = to_host(r.ids)
+        for i in range(ids.shape[0]):
+            fin = np.isfinite(rsc[i])
+            kth = rsc[i][fin][-1] if fin.any() else np.inf
+            strict = rsc[i] < kth * (1 - 1e-5) - 1e-5
+            assert set(ids[i][strict]) == set(rids[i][strict])
+
+
+def test_serve_matches_oracle_and_alone():
+    srv, reqs, stats, params = _serve()
+    assert stats.batches > 3
+    _check_oracle(srv, reqs, params)
+    # the same query alone (its own call, same watermark) gives the same bits
+    segs = [sg.index for sg in srv.segments]
+    for r in reqs:
+        if r.kind != "query":
+            continue
+        Q = to_dev(r.points)
+        qk = srv._hash(Q)
+        ids, sc, nc = lsh.lsh_query(segs, srv.base[:srv.n], Q, qk, k=10,
+                                    watermark=r.watermark, metric=srv.metric)
+        assert (to_host(ids) == to_host(r.ids)).all()
+        assert (to_host(sc).view(np.uint32) == to_host(r.score).view(np.uint32)).all()
+        assert (to_host(nc) == to_host(r.ncand)).all()
+
+
+def test_serve_merges_segments_and_keeps_budget():
+    # a budget below most requests: every request runs alone, so inserts
+    # create more than 16 segments and force merges
+    srv, reqs, stats, params = _serve(n_req=90, budget=1, family=lsh.SRP, w=1.0, seed=73)
+    assert stats.batches == len(reqs)
+    assert stats.merges >= 1 and len(srv.segments) <= serve.MAX_SEGMENTS
+    largest = max(srv._request_bytes(r) for r in reqs)
+    assert stats.peak_bytes <= 2 * largest
+    _check_oracle(srv, reqs, params)
+
+
+def test_serve_realtime_latency_fields():
+    srv, reqs, stats, _ = _serve(n_req=40, realtime=True)
+    summary = serve.summarize(reqs, stats, max(r.done for r in reqs))
+    assert summary["queries"] + summary["inserts"] == 40
+    assert all(np.isfinite(r.done) and r.done >= 0 for r in reqs)
