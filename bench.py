@@ -232,7 +232,12 @@ def main():
         del X, keys, mem, ws
         index_holder.clear()
         torch.cuda.empty_cache()
-        extra["query_latency"] = query_latency(torch, lsh, synth, dev)
+        extra["query_latency"], extra["serving"] = query_latency(torch, lsh, synth, dev)
+        torch.cuda.empty_cache()
+        extra["hcs_vs_cs"] = hcs_throughput(torch, lsh, dev)
+        torch.cuda.empty_cache()
+        extra["precision"] = precision_path(torch, lsh, dev)
+        torch.cuda.empty_cache()
         res["extras"] = extra
 
     # ---------------------------------------------------------------- CPU oracle
@@ -274,7 +279,131 @@ def query_latency(torch, lsh, synth, dev):
                     "queries_per_s": round(bs / (med * 1e-3), 1),
                     "mean_candidates": round(float(nc.float().mean().item()), 1)})
         print(f"[bench] query {out[-1]}", file=sys.stderr, flush=True)
-    return {"workload": wl.name, "k": 10, "batches": out}
+    lat = {"workload": wl.name, "k": 10, "batches": out}
+    del idx, keys
+    torch.cuda.empty_cache()
+    return lat, serving(torch, synth, dev, wl, X, hd, sd, bd)
+
+
+def serving(torch, synth, dev, wl, X, hd, sd, bd):
+    """Continuously batched query/insert stream against the same index: a
+    sustainable Poisson rate and the planned 50,000 req/s (overload)."""
+    from paper_2503_06737_amd import serve
+    qpool = wl.points(400_000, stream=1)
+    ipool = wl.points(100_000, stream=2)
+    cur = {"q": 0, "i": 0}
+
+    def src(pool, key):
+        def take(m):
+            lo = cur[key] % (pool.shape[0] - m)
+            cur[key] = lo + m
+            return pool[lo:lo + m]
+        return take
+
+    out = {}
+    for name, rate, n_req in (("sustained", 600.0, 1200), ("planned_overload", 50_000.0, 800)):
+        reqs = serve.poisson_stream(n_req, rate, 0.9, 4096, wl.d, src(qpool, "q"),
+                                    src(ipool, "i"), wl.seed + 3)
+        cap = X.shape[0] + sum(r.points.shape[0] for r in reqs if r.kind == "insert")
+        srv = serve.Server(X, hd, sd, bd, K=wl.K, L=wl.L, w=wl.w, capacity=cap,
+                           budget_bytes=2 << 30, k=10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = srv.serve(reqs, realtime=True)
+        wall = time.perf_counter() - t0
+        summ = serve.summarize(reqs, st, wall)
+        summ.update({"offered_req_per_s": rate, "query_frac": 0.9, "max_points": 4096})
+        out[name] = summ
+        print(f"[bench] serving {name}: {summ}", file=sys.stderr, flush=True)
+        del srv
+        torch.cuda.empty_cache()
+    out["workload"] = wl.name + " base, fresh query (stream 1) and insert (stream 2) draws"
+    return out
+
+
+def _device_clusters(torch, n, d, n_centres, sigma, seed, dev):
+    """Gaussian clusters drawn on the device (seeded): the recipe of the
+    cluster workloads, without a multi-GB host transfer."""
+    g = torch.Generator(device=dev).manual_seed(seed)
+    mu = torch.randn((n_centres, d), generator=g, device=dev)
+    c = torch.randint(0, n_centres, (n,), generator=g, device=dev)
+    x = torch.empty((n, d), device=dev)
+    step = 65536
+    for lo in range(0, n, step):
+        hi = min(n, lo + step)
+        x[lo:hi] = mu[c[lo:hi]] + sigma * torch.randn((hi - lo, d), generator=g, device=dev)
+    return x
+
+
+def hcs_throughput(torch, lsh, dev):
+    """HCS (N = 2 and 3) vs CS hashing at m = 1024 on 500k x 4096 clusters."""
+    from paper_2503_06737_amd import synth
+    n, d, K, L, w = 500_000, 4096, 16, 64, 4.0
+    X = _device_clusters(torch, n, d, 200, 0.2, 250306737 + 3000, dev)
+    h, s = synth.cs_state(d, K * L, 7)
+    b = torch.from_numpy(synth.shifts(K * L, w, 7)).to(dev)
+    hd, sd = torch.from_numpy(h.view(np.int32)).to(dev), torch.from_numpy(s).to(dev)
+    bytes_pp = d * 4 + 8 * L
+    res = {"n": n, "d": d, "m": K * L, "K": K, "L": L}
+
+    def bench_fn(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        med, _ = timed(torch, fn, 5)
+        return {"ms": round(med, 4), "gbs": round(n * bytes_pp / (med * 1e-3) / 1e9, 1)}
+
+    res["cs"] = bench_fn(lambda: lsh.lsh_hash_cs(X, hd, sd, family=0, K=K, L=L, w=w, b=b))
+    for name, dk, mk in (("hcs_n2", (64, 64), (32, 32)), ("hcs_n3", (16, 16, 16), (8, 8, 16))):
+        hk, sk = synth.hcs_state(dk, mk, 7)
+        hkd = torch.from_numpy(np.concatenate(hk).view(np.int32)).to(dev)
+        skd = torch.from_numpy(np.concatenate(sk)).to(dev)
+        res[name] = bench_fn(lambda: lsh.lsh_hash_hcs(X, dk, mk, hkd, skd, family=0, K=K, L=L,
+                                                      w=w, b=b))
+        res[name]["dk"], res[name]["mk"] = list(dk), list(mk)
+    print(f"[bench] hcs_vs_cs {res}", file=sys.stderr, flush=True)
+    del X
+    return res
+
+
+def precision_path(torch, lsh, dev):
+    """BF16 / FP8-E4M3FN points with a per-row scale (200k x 16384 clusters,
+    K=16, L=32, m=512): hashing with and without the FP64 near-edge recheck.
+    recomputed = components re-evaluated in FP64; changed = those whose FP32
+    code differed (the fast path's disagreement with the FP64 evaluation)."""
+    from paper_2503_06737_amd import synth
+    n, d, K, L, w = 200_000, 16_384, 16, 32, 4.0
+    X = _device_clusters(torch, n, d, 50, 0.1, 250306737 + 4000, dev)
+    amax = X.abs().amax(dim=1).clamp_min(1e-30)
+    h, s = synth.cs_state(d, K * L, 9)
+    hd, sd = torch.from_numpy(h.view(np.int32)).to(dev), torch.from_numpy(s).to(dev)
+    b = torch.from_numpy(synth.shifts(K * L, w, 9)).to(dev)
+    res = {"n": n, "d": d, "K": K, "L": L, "m": K * L}
+    for name, dt, qmax, esz in (("bf16", torch.bfloat16, 1.0, 2), ("fp8_e4m3fn",
+                                                                    torch.float8_e4m3fn, 448.0, 1)):
+        scale = (amax / qmax).float()
+        q = (X / scale[:, None]).clamp(-qmax, qmax).to(dt)
+        bytes_pp = d * esz + 4 + 8 * L
+        e = {}
+        for rc in (False, True):
+            fn = lambda c=None: lsh.lsh_hash_cs(q, hd, sd, family=0, K=K, L=L, w=w, b=b,
+                                                scale=scale, recheck=rc, counters=c)
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            med, _ = timed(torch, fn, 5)
+            c = torch.zeros(4, dtype=torch.int64, device=dev)
+            fn(c)
+            cnt = c.cpu().numpy()
+            e["recheck" if rc else "fast"] = {
+                "ms": round(med, 4), "gbs": round(n * bytes_pp / (med * 1e-3) / 1e9, 1),
+                **({"recomputed": int(cnt[0]), "changed": int(cnt[1]),
+                    "changed_per_million_codes": round(cnt[1] / (n * K * L) * 1e6, 3)} if rc else {})}
+        res[name] = e
+        print(f"[bench] precision {name}: {e}", file=sys.stderr, flush=True)
+        del q
+    del X
+    return res
 
 
 def cpu_baseline(x_host, h, s, b, K, L, w):
