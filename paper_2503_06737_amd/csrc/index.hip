@@ -5,7 +5,7 @@
 // run heads.  Keys are 64-bit digests (E2LSH) or K sign bits (SRP), so the
 // order is built most-significant-digit first:
 //   1. mask    - OR and AND of every key of a table: the bits that vary;
-//   2. msd     - the top B varying bits (B grows with n, at most 9) form the
+//   2. msd     - the top B varying bits (B grows with n, at most 10) form the
 //                segment digit: per-tile digit counts, their scan (segment
 //                starts) and a stable scatter of (key, id) into 2^B segments
 //                per table;
@@ -31,14 +31,14 @@ constexpr int kThreads = 1024;             // scatter / big-segment workgroups
 constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;   // 8192 keys per scatter tile
 constexpr int kWaves = kThreads / kWave;
-constexpr int kMsdBitsMax = 9;
+constexpr int kMsdBitsMax = 10;
 constexpr int kMsdRadixMax = 1 << kMsdBitsMax;
 constexpr int kRadix = 256;                // 8-bit digits below the segment digit
 constexpr int kSegThreads = 512;
 constexpr int kSegSmall = kSegThreads * kItems; // 4096: segments sorted by kSegThreads
 constexpr int kSegLarge = kThreads * kItems;    // 8192: parts sorted inside the big path
 constexpr int kChunks = 8;     // 8-bit chunks of a key (a segment's varying bits lie below its digit)
-constexpr int kFastChunks = 4; // chunks sorted before the adjacent-pair check
+constexpr int kFastChunks = 3; // chunks sorted before the adjacent-pair check
 constexpr int kStackMax = 16 * kRadix; // pending parts of one big segment
 
 constexpr int kHeadThreads = 256;
@@ -272,9 +272,10 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
 template <int RMAX> struct ScatterLds {
     uint64_t key[kTile];
     uint32_t id[kTile];
-    uint32_t whist[kWaves][RMAX];
+    uint16_t whist[kWaves][RMAX]; // per-wave digit counts (at most 512)
     uint32_t lbase[RMAX];
     uint32_t wsum[RMAX / kWave];
+    uint32_t count[RMAX]; // the tile's count of each digit (for the caller)
 };
 
 // Stable scatter of one tile (1024 threads): keys (and ids, or id0 + i when
@@ -282,8 +283,8 @@ template <int RMAX> struct ScatterLds {
 // tile's keys of that digit), digit = (key >> shift) & (2^bits - 1).  Wave w
 // ranks rows w*8 .. w*8+7 of 64 keys; the lanes holding the same digit come
 // from one ballot per digit bit.  The tile is reordered in LDS and written
-// as contiguous digit runs.  On return s.whist[0][d] holds the tile's count
-// of digit d.
+// as contiguous digit runs.  On return s.count[d] holds the tile's count of
+// digit d.
 template <int RMAX>
 __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t *kin,
                                              const uint32_t *iin, uint32_t id0, int cnt,
@@ -328,7 +329,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (before == 0)
-            s.whist[wid][dg[it]] = old + __popcll(peers);
+            s.whist[wid][dg[it]] = (uint16_t)(old + __popcll(peers));
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         rank[it] = old + before;
@@ -343,7 +344,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
             c[w] = s.whist[w][tid];
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
-            s.whist[w][tid] = tot;
+            s.whist[w][tid] = (uint16_t)tot; // prefix within the tile: < 8192
             tot += c[w];
         }
     }
@@ -373,7 +374,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
     if (tid < R) {
         // the last digit also holds the padding, which ranks after its keys
         const uint32_t nxt = tid + 1 < R ? s.lbase[tid + 1] : (uint32_t)cnt;
-        s.whist[0][tid] = nxt - s.lbase[tid];
+        s.count[tid] = nxt - s.lbase[tid];
     }
     __syncthreads();
 }
@@ -908,7 +909,7 @@ __global__ __launch_bounds__(kThreads) void big_sort_kernel(BuildArgs a)
                 const int cnt = (int)min((uint32_t)kTile, size - base);
                 big_scatter(s.u.sc, kin + base, iin + base, cnt, shift, s.run, ko, io);
                 if (tid < kRadix)
-                    s.run[tid] += s.u.sc.whist[0][tid];
+                    s.run[tid] += s.u.sc.count[tid];
                 __syncthreads();
             }
         }
@@ -1087,7 +1088,9 @@ struct WsLayout {
     int ntiles, nhtiles, bits, big_grid;
 };
 
-// Segment digit width: about 2048 keys per segment, at most 2^9 segments.
+// Segment digit width: about 2048 keys per segment (a workgroup per
+// segment has a fixed cost, so segments are not made smaller than that), at
+// most 2^10 segments.
 int msd_bits_for(int64_t n)
 {
     int b = 1;
