@@ -59,10 +59,15 @@ struct BuildArgs {
     uint32_t *seg_start;  // [L][2^B]
     uint64_t *ka, *kb;    // key buffers [L][n]; kb ends sorted
     uint32_t *ia, *ids;   // id buffers [L][n] (ids = the index's sorted_ids)
-    uint32_t *blist;      // [L * 2^B][2]: table, segment of the big segments
-    uint32_t *bcount;     // [2]: big segments, stack overflows (0 unless a bound fails)
+    uint32_t *blist;      // [L * 2^B][8]: table, segment, first tile, tiles, pivot?, #<, #=
+    uint64_t *bpivot;     // [L * 2^B]: pivot key of a big segment
+    uint32_t *btile;      // [maxbt][2]: big segment, tile within it
+    uint32_t *tcls;       // [maxbt][4]: per tile: class counts, then class offsets
+    uint32_t *bcount;     // [3]: big segments, stack overflows (0 unless a bound fails), tiles
     uint32_t *stack;      // [grid][kStackMax][3]: start, size, buffer
 };
+
+constexpr int kBig = 8; // words per big-segment entry
 
 __device__ __forceinline__ int top_shift(uint64_t vm, int bits)
 {
@@ -112,7 +117,7 @@ __global__ __launch_bounds__(256) void build_init_kernel(BuildArgs a)
             a.tor[i] = 0;
             a.tand[i] = ~0ull;
         }
-        if (i < 2)
+        if (i < 3)
             a.bcount[i] = 0;
     }
 }
@@ -591,35 +596,260 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(BuildArgs a)
 
 // --------------------------------------------------------- big segments
 
-// One workgroup lists the segments larger than kSegSmall.
+// One workgroup lists the segments larger than kSegSmall and their tiles.
 __global__ __launch_bounds__(kThreads) void big_plan_kernel(BuildArgs a)
 {
-    __shared__ uint32_t part[kThreads];
+    __shared__ uint32_t part[kThreads], tpart[kThreads];
     const int tid = threadIdx.x;
     const int nseg = a.L << a.msd_bits;
     const int per = (nseg + kThreads - 1) / kThreads;
     const int lo = tid * per, hi = min(nseg, lo + per);
-    uint32_t nb = 0;
-    for (int e = lo; e < hi; ++e)
-        nb += a.ghist[e] > (uint32_t)kSegSmall;
+    uint32_t nb = 0, nt = 0;
+    for (int e = lo; e < hi; ++e) {
+        const uint32_t c = a.ghist[e];
+        if (c > (uint32_t)kSegSmall) {
+            ++nb;
+            nt += (c + kTile - 1) / kTile;
+        }
+    }
     part[tid] = nb;
+    tpart[tid] = nt;
     __syncthreads();
     for (int o = 1; o < kThreads; o <<= 1) {
         const uint32_t u = tid >= o ? part[tid - o] : 0;
+        const uint32_t v = tid >= o ? tpart[tid - o] : 0;
         __syncthreads();
         part[tid] += u;
+        tpart[tid] += v;
         __syncthreads();
     }
-    uint32_t bi = part[tid] - nb;
+    uint32_t bi = part[tid] - nb, ti = tpart[tid] - nt;
     for (int e = lo; e < hi; ++e) {
-        if (a.ghist[e] > (uint32_t)kSegSmall) {
-            a.blist[2 * bi] = (uint32_t)(e >> a.msd_bits);
-            a.blist[2 * bi + 1] = (uint32_t)(e & ((1 << a.msd_bits) - 1));
+        const uint32_t c = a.ghist[e];
+        if (c > (uint32_t)kSegSmall) {
+            const uint32_t ntl = (c + kTile - 1) / kTile;
+            uint32_t *b = a.blist + kBig * bi;
+            b[0] = (uint32_t)(e >> a.msd_bits);
+            b[1] = (uint32_t)(e & ((1 << a.msd_bits) - 1));
+            b[2] = ti;
+            b[3] = ntl;
+            b[4] = 0;
+            for (uint32_t k = 0; k < ntl; ++k) {
+                a.btile[2 * (ti + k)] = bi;
+                a.btile[2 * (ti + k) + 1] = k;
+            }
             ++bi;
+            ti += ntl;
         }
     }
-    if (tid == kThreads - 1)
+    if (tid == kThreads - 1) {
         a.bcount[0] = part[tid];
+        a.bcount[2] = tpart[tid];
+    }
+}
+
+// A key that fills at least 16 of 64 evenly spaced samples of keys[0, size)
+// (wave 0 of the block decides; lowest lane on ties).  Returns the count
+// (0 for lanes other than lane 0 of wave 0) and the key in *pivot.
+__device__ __forceinline__ uint32_t sample_pivot(const uint64_t *kin, uint32_t size,
+                                                 uint64_t *pivot)
+{
+    const int tid = threadIdx.x;
+    uint32_t best = 0;
+    uint64_t ks = 0;
+    if (tid < kWave) {
+        ks = kin[(uint64_t)tid * size / kWave];
+        uint32_t c = 0;
+        for (int j = 0; j < kWave; ++j) {
+            const uint64_t kj = ((uint64_t)(uint32_t)__shfl((int)(ks >> 32), j, kWave) << 32) |
+                                (uint32_t)__shfl((int)(uint32_t)ks, j, kWave);
+            c += kj == ks;
+        }
+        best = (c << 8) | (uint32_t)(kWave - 1 - tid);
+        for (int o = 32; o >= 1; o >>= 1)
+            best = max(best, (uint32_t)__shfl_xor((int)best, o, kWave));
+        if ((uint32_t)(kWave - 1 - tid) == (best & 255u))
+            *pivot = ks;
+    }
+    return best >> 8;
+}
+
+// Per big segment (in ka / ia after the segment scatter): the pivot, if any.
+__global__ __launch_bounds__(kWave) void big_pivot_kernel(BuildArgs a)
+{
+    const uint32_t nb = a.bcount[0];
+    for (uint32_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+        uint32_t *b = a.blist + kBig * bi;
+        const int e = ((int)b[0] << a.msd_bits) + (int)b[1];
+        const uint64_t *kin = a.ka + (int64_t)b[0] * a.n + a.seg_start[e];
+        __shared__ uint64_t pv;
+        const uint32_t c = sample_pivot(kin, a.ghist[e], &pv);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            b[4] = c >= 16;
+            a.bpivot[bi] = pv;
+        }
+        __syncthreads();
+    }
+}
+
+// Per tile of a big segment with a pivot: counts of keys <, ==, > pivot.
+__global__ __launch_bounds__(256) void big_count_kernel(BuildArgs a)
+{
+    const uint32_t nt = a.bcount[2];
+    __shared__ uint32_t sc[256 / kWave][2];
+    for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
+        const uint32_t bi = a.btile[2 * j], k = a.btile[2 * j + 1];
+        const uint32_t *b = a.blist + kBig * bi;
+        if (!b[4])
+            continue;
+        const int e = ((int)b[0] << a.msd_bits) + (int)b[1];
+        const uint32_t size = a.ghist[e];
+        const uint32_t cnt = min((uint32_t)kTile, size - k * kTile);
+        const uint64_t *kin = a.ka + (int64_t)b[0] * a.n + a.seg_start[e] + (int64_t)k * kTile;
+        const uint64_t pivot = a.bpivot[bi];
+        uint32_t nlt = 0, neq = 0;
+        for_each_key(kin, cnt, [&](uint32_t, uint64_t key) {
+            nlt += key < pivot;
+            neq += key == pivot;
+        });
+        nlt = wave_sum(nlt);
+        neq = wave_sum(neq);
+        if (lane_id() == 0) {
+            sc[threadIdx.x / kWave][0] = nlt;
+            sc[threadIdx.x / kWave][1] = neq;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t l = 0, q = 0;
+            for (int w = 0; w < 256 / kWave; ++w) {
+                l += sc[w][0];
+                q += sc[w][1];
+            }
+            a.tcls[4 * j] = l;
+            a.tcls[4 * j + 1] = q;
+            a.tcls[4 * j + 2] = cnt - l - q;
+        }
+        __syncthreads();
+    }
+}
+
+// Per big segment with a pivot: class sizes and each tile's class offsets
+// (table positions: the < keys first, then the == run, then the > keys).
+__global__ __launch_bounds__(kWave) void big_cscan_kernel(BuildArgs a)
+{
+    const uint32_t nb = a.bcount[0];
+    for (uint32_t bi = blockIdx.x * kWave + threadIdx.x; bi < nb; bi += gridDim.x * kWave) {
+        uint32_t *b = a.blist + kBig * bi;
+        if (!b[4])
+            continue;
+        const int e = ((int)b[0] << a.msd_bits) + (int)b[1];
+        uint32_t nlt = 0, neq = 0;
+        for (uint32_t k = 0; k < b[3]; ++k) {
+            nlt += a.tcls[4 * (b[2] + k)];
+            neq += a.tcls[4 * (b[2] + k) + 1];
+        }
+        uint32_t o0 = a.seg_start[e], o1 = o0 + nlt, o2 = o1 + neq;
+        for (uint32_t k = 0; k < b[3]; ++k) {
+            uint32_t *c = a.tcls + 4 * (b[2] + k);
+            const uint32_t c0 = c[0], c1 = c[1], c2 = c[2];
+            c[0] = o0;
+            c[1] = o1;
+            c[2] = o2;
+            o0 += c0;
+            o1 += c1;
+            o2 += c2;
+        }
+        b[5] = nlt;
+        b[6] = neq;
+    }
+}
+
+// Stable 3-way partition of keys [0, cnt) around pivot: class 0 (key <
+// pivot), 1 (==), 2 (>) go to kout/iout at base[class] + (rank among the
+// keys of that class).  Tiles of 8192 keys in order; wave w ranks rows
+// w*8 .. w*8+7 of 64 keys with two ballots; base[] (LDS) advances per tile.
+__device__ __noinline__ void partition3(uint32_t (*cls)[4], const uint64_t *kin,
+                                        const uint32_t *iin, uint32_t cnt, uint64_t pivot,
+                                        uint32_t *base, uint64_t *kout, uint32_t *iout)
+{
+    const int tid = threadIdx.x, wid = tid / kWave, lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t t0 = 0; t0 < cnt; t0 += kTile) {
+        uint32_t cl[kItems], rank[kItems];
+        uint32_t r0 = 0, r1 = 0, r2 = 0; // this wave's running class counts
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
+            uint32_t c = 3;
+            if (i < cnt) {
+                const uint64_t k = kin[i];
+                c = k < pivot ? 0u : (k == pivot ? 1u : 2u);
+            }
+            const uint64_t b0 = __ballot(c == 0), b1 = __ballot(c == 1), b2 = __ballot(c == 2);
+            const uint64_t mine = c == 0 ? b0 : (c == 1 ? b1 : b2);
+            rank[it] = (c == 0 ? r0 : (c == 1 ? r1 : r2)) + __popcll(mine & lt);
+            r0 += __popcll(b0);
+            r1 += __popcll(b1);
+            r2 += __popcll(b2);
+            cl[it] = c;
+        }
+        if (lane == 0) {
+            cls[wid][0] = r0;
+            cls[wid][1] = r1;
+            cls[wid][2] = r2;
+        }
+        __syncthreads();
+        uint32_t p0 = 0, p1 = 0, p2 = 0; // class counts of the earlier waves
+        for (int w = 0; w < wid; ++w) {
+            p0 += cls[w][0];
+            p1 += cls[w][1];
+            p2 += cls[w][2];
+        }
+        const uint32_t q0 = base[0] + p0, q1 = base[1] + p1, q2 = base[2] + p2;
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t c = cl[it];
+            if (c < 3) {
+                const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
+                const uint32_t pos = (c == 0 ? q0 : (c == 1 ? q1 : q2)) + rank[it];
+                kout[pos] = kin[i];
+                iout[pos] = iin[i];
+            }
+        }
+        __syncthreads();
+        if (tid < 3) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kWaves; ++w)
+                tot += cls[w][tid];
+            base[tid] += tot;
+        }
+        __syncthreads();
+    }
+}
+
+// Per tile of a big segment with a pivot: the stable 3-way scatter from
+// ka / ia to kb / ids (the == run lands in its final place).
+__global__ __launch_bounds__(kThreads) void big_part_kernel(BuildArgs a)
+{
+    __shared__ uint32_t cls[kWaves][4];
+    __shared__ uint32_t base[4];
+    const uint32_t nt = a.bcount[2];
+    for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
+        const uint32_t bi = a.btile[2 * j], k = a.btile[2 * j + 1];
+        const uint32_t *b = a.blist + kBig * bi;
+        if (!b[4])
+            continue;
+        const int e = ((int)b[0] << a.msd_bits) + (int)b[1];
+        const uint32_t cnt = min((uint32_t)kTile, a.ghist[e] - k * kTile);
+        const int64_t tb = (int64_t)b[0] * a.n;
+        const int64_t start = tb + a.seg_start[e] + (int64_t)k * kTile;
+        if (threadIdx.x < 3)
+            base[threadIdx.x] = a.tcls[4 * j + threadIdx.x];
+        __syncthreads();
+        partition3(cls, a.ka + start, a.ia + start, cnt, a.bpivot[bi], base, a.kb + tb,
+                   a.ids + tb);
+    }
 }
 
 struct BigLds {
@@ -636,68 +866,6 @@ struct BigLds {
     uint32_t pivot_cnt;
     int top;
 };
-
-// Stable 3-way partition of keys [0, cnt) around pivot: class 0 (key <
-// pivot), 1 (==), 2 (>) go to kout/iout at base[class] + (rank among the
-// part's keys of that class).  Tiles of 8192 keys in order; wave w ranks
-// rows w*8 .. w*8+7 of 64 keys with two ballots; base[] advances per tile.
-__device__ __noinline__ void partition3(BigLds &s, const uint64_t *kin, const uint32_t *iin, uint32_t cnt,
-                           uint64_t pivot, uint32_t *base, uint64_t *kout, uint32_t *iout)
-{
-    const int tid = threadIdx.x, wid = tid / kWave, lane = lane_id();
-    const uint64_t lt = lanemask_lt();
-    for (uint32_t t0 = 0; t0 < cnt; t0 += kTile) {
-        uint32_t cls[kItems], rank[kItems];
-        uint32_t r0 = 0, r1 = 0, r2 = 0; // this wave's running class counts
-#pragma unroll
-        for (int it = 0; it < kItems; ++it) {
-            const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
-            uint32_t c = 3;
-            if (i < cnt) {
-                const uint64_t k = kin[i];
-                c = k < pivot ? 0u : (k == pivot ? 1u : 2u);
-            }
-            const uint64_t b0 = __ballot(c == 0), b1 = __ballot(c == 1), b2 = __ballot(c == 2);
-            const uint64_t mine = c == 0 ? b0 : (c == 1 ? b1 : b2);
-            rank[it] = (c == 0 ? r0 : (c == 1 ? r1 : r2)) + __popcll(mine & lt);
-            r0 += __popcll(b0);
-            r1 += __popcll(b1);
-            r2 += __popcll(b2);
-            cls[it] = c;
-        }
-        if (lane == 0) {
-            s.cls[wid][0] = r0;
-            s.cls[wid][1] = r1;
-            s.cls[wid][2] = r2;
-        }
-        __syncthreads();
-        uint32_t p0 = 0, p1 = 0, p2 = 0; // class counts of the earlier waves
-        for (int w = 0; w < wid; ++w) {
-            p0 += s.cls[w][0];
-            p1 += s.cls[w][1];
-            p2 += s.cls[w][2];
-        }
-        const uint32_t q0 = base[0] + p0, q1 = base[1] + p1, q2 = base[2] + p2;
-#pragma unroll
-        for (int it = 0; it < kItems; ++it) {
-            const uint32_t c = cls[it];
-            if (c < 3) {
-                const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
-                const uint32_t pos = (c == 0 ? q0 : (c == 1 ? q1 : q2)) + rank[it];
-                kout[pos] = kin[i];
-                iout[pos] = iin[i];
-            }
-        }
-        __syncthreads();
-        if (tid < 3) {
-            uint32_t tot = 0;
-            for (int w = 0; w < kWaves; ++w)
-                tot += s.cls[w][tid];
-            base[tid] += tot;
-        }
-        __syncthreads();
-    }
-}
 
 // The big path calls these out of line: inlined together with the
 // partition they exceed the register budget of a 1024-thread workgroup.
@@ -734,14 +902,37 @@ __global__ __launch_bounds__(kThreads) void big_sort_kernel(BuildArgs a)
     const uint32_t nb = a.bcount[0];
     uint32_t *stk = a.stack + (size_t)blockIdx.x * kStackMax * 3;
     for (uint32_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
-        const int t = (int)a.blist[2 * bi];
-        const int e = (t << a.msd_bits) + (int)a.blist[2 * bi + 1];
+        const uint32_t *b = a.blist + kBig * bi;
+        const int t = (int)b[0];
+        const int e = (t << a.msd_bits) + (int)b[1];
         const int64_t tb = (int64_t)t * a.n;
         if (tid == 0) {
-            stk[0] = a.seg_start[e];
-            stk[1] = a.ghist[e];
-            stk[2] = 0;
-            s.top = 1;
+            // a segment split around its pivot by the parallel partition
+            // leaves its < and > keys in kb / ids (the == run is final);
+            // any other starts whole in ka / ia
+            int tp = 0;
+            const uint32_t st = a.seg_start[e], size = a.ghist[e];
+            if (b[4]) {
+                const uint32_t nlt = b[5], neq = b[6];
+                if (nlt) {
+                    stk[3 * tp] = st;
+                    stk[3 * tp + 1] = nlt;
+                    stk[3 * tp + 2] = 1;
+                    ++tp;
+                }
+                if (size - nlt - neq) {
+                    stk[3 * tp] = st + nlt + neq;
+                    stk[3 * tp + 1] = size - nlt - neq;
+                    stk[3 * tp + 2] = 1;
+                    ++tp;
+                }
+            } else {
+                stk[0] = st;
+                stk[1] = size;
+                stk[2] = 0;
+                tp = 1;
+            }
+            s.top = tp;
         }
         __syncthreads();
         while (true) {
@@ -764,22 +955,10 @@ __global__ __launch_bounds__(kThreads) void big_sort_kernel(BuildArgs a)
             }
             // a key that fills at least a quarter of 64 evenly spaced samples
             // is split off by a stable 3-way partition: its run is final
-            if (tid < kWave) {
-                const uint64_t ks = kin[(uint64_t)tid * size / kWave];
-                uint32_t c = 0;
-                for (int j = 0; j < kWave; ++j) {
-                    const uint64_t kj = ((uint64_t)(uint32_t)__shfl((int)(ks >> 32), j, kWave) << 32) |
-                                        (uint32_t)__shfl((int)(uint32_t)ks, j, kWave);
-                    c += kj == ks;
-                }
-                // largest count, lowest lane on ties
-                uint32_t best = (c << 8) | (uint32_t)(kWave - 1 - tid);
-                for (int o = 32; o >= 1; o >>= 1)
-                    best = max(best, (uint32_t)__shfl_xor((int)best, o, kWave));
-                if ((uint32_t)(kWave - 1 - tid) == (best & 255u)) {
-                    s.pivot = ks;
-                    s.pivot_cnt = best >> 8;
-                }
+            {
+                const uint32_t c = sample_pivot(kin, size, &s.pivot);
+                if (tid == 0)
+                    s.pivot_cnt = c;
             }
             __syncthreads();
             if (s.pivot_cnt >= 16) {
@@ -810,7 +989,7 @@ __global__ __launch_bounds__(kThreads) void big_sort_kernel(BuildArgs a)
                 __syncthreads();
                 uint64_t *ko = (buf ? a.ka : a.kb) + tb + start;
                 uint32_t *io = (buf ? a.ia : a.ids) + tb + start;
-                partition3(s, kin, iin, size, pivot, s.run, ko, io);
+                partition3(s.cls, kin, iin, size, pivot, s.run, ko, io);
                 if (tid == 0 && s.top + 3 > kStackMax) {
                     atomicAdd(&a.bcount[1], 1u); // cannot happen (see the bound above)
                 } else if (tid == 0) {
@@ -1083,9 +1262,9 @@ IndexLayout index_layout(int64_t n, int32_t L)
 }
 
 struct WsLayout {
-    size_t ka, kb, ia, tor, tand, tile_hist, ghist, seg_start, blist, bcount, stack, tile_cnt,
-        total;
-    int ntiles, nhtiles, bits, big_grid;
+    size_t ka, kb, ia, tor, tand, tile_hist, ghist, seg_start, blist, bpivot, btile, tcls, bcount,
+        stack, tile_cnt, total;
+    int ntiles, nhtiles, bits, big_grid, maxbt;
 };
 
 // Segment digit width: about 2048 keys per segment (a workgroup per
@@ -1124,7 +1303,13 @@ WsLayout ws_layout(int64_t n, int32_t L)
     w.tile_hist = take(((size_t)L * w.ntiles << w.bits) * 4);
     w.ghist = take(nseg * 4);
     w.seg_start = take(nseg * 4);
-    w.blist = take(nseg * 8);
+    // tiles of the big segments: sum of ceil(c / kTile) <= L * n / kTile + (number of
+    // big segments) <= L * n / kTile + L * 2^B
+    w.maxbt = (int)((size_t)L * n / kTile + nseg + 1);
+    w.blist = take(nseg * kBig * 4);
+    w.bpivot = take(nseg * 8);
+    w.btile = take((size_t)w.maxbt * 8);
+    w.tcls = take((size_t)w.maxbt * 16);
     w.bcount = take(16);
     w.stack = take((size_t)w.big_grid * kStackMax * 12);
     w.tile_cnt = take((size_t)L * (w.nhtiles > 0 ? w.nhtiles : 1) * 4);
@@ -1222,6 +1407,9 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     ba.ia = (uint32_t *)(wb + wl.ia);
     ba.ids = idx->sorted_ids;
     ba.blist = (uint32_t *)(wb + wl.blist);
+    ba.bpivot = (uint64_t *)(wb + wl.bpivot);
+    ba.btile = (uint32_t *)(wb + wl.btile);
+    ba.tcls = (uint32_t *)(wb + wl.tcls);
     ba.bcount = (uint32_t *)(wb + wl.bcount);
     ba.stack = (uint32_t *)(wb + wl.stack);
 
@@ -1249,6 +1437,10 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     hipLaunchKernelGGL(msd_scatter_kernel, tiles, dim3(kThreads), scatter_lds, s, ba);
     hipLaunchKernelGGL(seg_sort_kernel, dim3(1 << wl.bits, L), dim3(kSegThreads), seg_lds, s, ba);
     hipLaunchKernelGGL(big_plan_kernel, dim3(1), dim3(kThreads), 0, s, ba);
+    hipLaunchKernelGGL(big_pivot_kernel, dim3(wl.big_grid), dim3(kWave), 0, s, ba);
+    hipLaunchKernelGGL(big_count_kernel, dim3(4 * wl.big_grid), dim3(256), 0, s, ba);
+    hipLaunchKernelGGL(big_cscan_kernel, dim3(wl.big_grid), dim3(kWave), 0, s, ba);
+    hipLaunchKernelGGL(big_part_kernel, dim3(2 * wl.big_grid), dim3(kThreads), 0, s, ba);
     hipLaunchKernelGGL(big_sort_kernel, dim3(wl.big_grid), dim3(kThreads), big_lds, s, ba);
 
     HeadArgs ha;
