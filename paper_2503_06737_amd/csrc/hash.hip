@@ -92,13 +92,14 @@ struct HashArgs {
     int32_t waves;       // waves per workgroup
     int32_t mpad;        // bin slots per wave (bins, pad words, trash), multiple of 4
     int32_t wave_region; // LDS bytes per wave region: a power of two >= 4 * mpad
-    int32_t tab_entries; // table entries: 64 * CH * VEC (rows padded to whole chunks)
+    int32_t tab_entries; // table entries: 64 * CH * VEC * pieces (rows padded to whole chunks)
     int32_t tab_off, bl_off, hinit_off, mask_off; // LDS byte offsets
     // key staging (stage_stride 0: keys are stored straight to memory):
     // key of table t for row slot i of the block is at LDS byte
     // stage_base + (t >> stage_tpc_log2) * stage_stride
     //            + ((t & (2^stage_tpc_log2 - 1)) * (RB + 1) + i) * 8
     int32_t stage_base, stage_stride, stage_tpc_log2;
+    int32_t pieces; // long rows: pieces of 64 * CH chunks per row (even); 1 otherwise
 };
 
 __device__ __forceinline__ uint32_t stage_addr(const HashArgs &a, int t, int slot)
@@ -598,15 +599,15 @@ __device__ void epilogue_srp(const HashArgs &a, const uint32_t *tab, const WaveL
 template <int DT, bool ALIGNED> constexpr int ALIGNED_VEC() { return ALIGNED ? Elem<DT>::per16 : 1; }
 
 // CH: 16-byte chunks (ALIGNED) or single elements per lane per row; a row
-// has at most 64 * CH of them.
+// has at most 64 * CH of them, unless LONG: then the row is read in
+// a.pieces pieces of 64 * CH chunks, the next piece prefetched.
 //
 // LDS image of a workgroup (offsets in HashArgs):
 //   [wave regions: waves x wave_region bytes, each holding mpad int32 bins]
 //   [table: tab_entries u32] [b/w or b: bin_pos(m) floats] [digest seeds]
 //   [SRP masks: waves x ceil(m/64) u64]
-template <int FAM, int DT, bool ALIGNED, bool RECHECK, int CH>
-// small rows: registers capped so that two workgroups fit per CU (the LDS
-// limit); long rows keep their whole row in registers instead
+template <int FAM, int DT, bool ALIGNED, bool RECHECK, int CH, bool LONG>
+// registers capped so that two workgroups fit per CU (the LDS limit)
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CH * ALIGNED_VEC<DT, ALIGNED>() <= 16 ? 4 : 1)))
 void hash_kernel(HashArgs a)
 {
@@ -684,11 +685,11 @@ void hash_kernel(HashArgs a)
     // Every lane issues exactly CH loads per row (chunks past the row end
     // re-read chunk 0 and are summed into trash), so the number of loads in
     // flight is static and each wait covers only the row being summed.
-    auto load_row = [&](Buf &buf, int64_t row) {
+    auto load_row = [&](Buf &buf, int64_t row, int32_t piece = 0) {
         const T *xr = (const T *)a.x + row * a.ld;
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            int32_t ch = i * kWave + lane;
+            int32_t ch = (piece * CH + i) * kWave + lane;
             ch = ch < nchunk ? ch : 0;
             if constexpr (ALIGNED) {
                 buf[i] = __builtin_nontemporal_load((const u32x4 *)(xr + (int64_t)ch * VEC));
@@ -705,7 +706,7 @@ void hash_kernel(HashArgs a)
 
     // table entries of this lane's chunks: kept in registers for the whole
     // kernel when there are at most 16 per lane
-    auto load_entries = [&](int i, uint32_t *tw) {
+    auto load_entries = [&](int i, uint32_t *tw) { // i: chunk of the row (piece * CH + i)
         const uint32_t *te = tab + (i * kWave + lane) * VEC;
         if constexpr (VEC == 1) {
             tw[0] = te[0];
@@ -720,13 +721,49 @@ void hash_kernel(HashArgs a)
             }
         }
     };
-    constexpr bool kTabRegs = CH * VEC <= 16;
+    constexpr bool kTabRegs = !LONG && CH * VEC <= 16;
     uint32_t treg[kTabRegs ? CH * VEC : 1];
     if constexpr (kTabRegs) {
 #pragma unroll
         for (int i = 0; i < CH; ++i)
             load_entries(i, treg + i * VEC);
     }
+
+    // 3. discretise and key.  k: the bins' scale (sum = bin * 2^-k), e: the
+    // row's exponent (|x| < 2^e), mb: the bits of max|x|, nres: times the
+    // bins were shifted right (each loses < 1 unit of 2^-k)
+    auto finish_row = [&](int64_t row, int slot, int k, int e, uint32_t mb, int nres) {
+        wave_sync();
+        RowFix rf;
+        rf.scale = row_scale_of<DT>(a, row);
+        rf.s2k = ldexp((double)rf.scale, -k);
+        rf.fs = (float)rf.s2k;
+        rf.af = rf.fs * a.alpha32 * a.inv_w32;
+        if constexpr (RECHECK) {
+            // truncation: each term off by < 2^-k (times the scale), a bin has
+            // <= c_max terms, plus one unit per shift; plus the FP64
+            // reference's own rounding (c_max^2 * 2^(e-52) bounds
+            // gamma_{c-1} * sum|terms|)
+            rf.ey = (double)rf.scale * ((double)(cmax + nres) * ldexp(1.0, -k) +
+                                        (double)cmax * (double)cmax * ldexp(1.0, e - 51));
+        } else {
+            rf.ey = 0.0;
+        }
+        // every code lies in [-128, 127] when sqrt(m) * scale * c_max * max|x| / w
+        // < 126: |sum| <= c_max * max|x| * 2^k (terms truncate toward zero)
+        // and b/w is in [0, 1); the margin covers the FP32 rounding of the bound
+        const bool narrow = a.alpha32 * rf.scale * (float)cmax * __uint_as_float(mb) * a.inv_w32 <
+                            126.0f;
+        if constexpr (FAM == LSH_E2LSH)
+            epilogue_e2lsh<DT, RECHECK>(a, tab, w, bl, hinit, row, slot, rf, narrow, nflag, nchg,
+                                        nsat);
+        else
+            epilogue_srp<DT, RECHECK>(a, tab, w, row, slot, rf, nflag, nchg);
+        wave_sync();
+        for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4)
+            *(int4 *)(w.bins + l) = make_int4(0, 0, 0, 0);
+        wave_sync();
+    };
 
     auto process_row = [&](const Buf &buf, int64_t row, int slot) {
         // 1. the row's largest magnitude -> exponent e (|x| < 2^e) -> k
@@ -770,37 +807,65 @@ void hash_kernel(HashArgs a)
             }
         }
 
-        // 3. discretise and key
-        wave_sync();
-        RowFix rf;
-        rf.scale = row_scale_of<DT>(a, row);
-        rf.s2k = ldexp((double)rf.scale, -k);
-        rf.fs = (float)rf.s2k;
-        rf.af = rf.fs * a.alpha32 * a.inv_w32;
-        if constexpr (RECHECK) {
-            // truncation: each term off by < 2^-k (times the scale), a bin has
-            // <= c_max terms; plus the FP64 reference's own rounding
-            // (c_max^2 * 2^(e-52) bounds gamma_{c-1} * sum|terms|)
-            rf.ey = (double)rf.scale * (double)cmax *
-                    (ldexp(1.0, -k) + (double)cmax * ldexp(1.0, e - 51));
-        } else {
-            rf.ey = 0.0;
-        }
-        // every code lies in [-128, 127] when sqrt(m) * scale * c_max * max|x| / w
-        // < 126: |sum| <= c_max * max|x| * 2^k (terms truncate toward zero)
-        // and b/w is in [0, 1); the margin covers the FP32 rounding of the bound
-        const bool narrow = a.alpha32 * rf.scale * (float)cmax * __uint_as_float(mb) * a.inv_w32 <
-                            126.0f;
-        if constexpr (FAM == LSH_E2LSH)
-            epilogue_e2lsh<DT, RECHECK>(a, tab, w, bl, hinit, row, slot, rf, narrow, nflag, nchg,
-                                        nsat);
-        else
-            epilogue_srp<DT, RECHECK>(a, tab, w, row, slot, rf, nflag, nchg);
-        wave_sync();
-        for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4)
-            *(int4 *)(w.bins + l) = make_int4(0, 0, 0, 0);
-        wave_sync();
+        finish_row(row, slot, k, e, mb, 0);
     };
+
+    // Long rows, piece p of a row: the bins' scale k follows the largest
+    // exponent seen so far (e_cur); when a piece raises it, the bins are
+    // shifted right by the difference first (nres counts the shifts: each
+    // floors a bin by less than one unit of the new 2^-k).  Terms then stay
+    // below 2^(31 - hr) as in the single-piece path.
+    int e_cur = 0, nres = 0;
+    uint32_t mb_row = 0;
+    auto piece = [&](const Buf &buf, int32_t p) {
+        float mx = 0.0f;
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                mx = fmaxf(mx, fabsf(chunk_value<DT, ALIGNED>(buf[i], e)));
+        const uint32_t mb = wave_max_u32(__float_as_uint(mx));
+        const int be = (int)((mb >> 23) & 0xffu);
+        const int ep = be == 0 ? -126 : be - 126;
+        if (p == 0) {
+            e_cur = ep;
+            nres = 0;
+            mb_row = mb;
+        } else {
+            mb_row = max(mb_row, mb);
+            if (ep > e_cur) {
+                const int sh = min(ep - e_cur, 31);
+                wave_sync();
+                for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4) {
+                    int4 v = *(const int4 *)(w.bins + l);
+                    v.x >>= sh;
+                    v.y >>= sh;
+                    v.z >>= sh;
+                    v.w >>= sh;
+                    *(int4 *)(w.bins + l) = v;
+                }
+                wave_sync();
+                e_cur = ep;
+                ++nres;
+            }
+        }
+        const int k = koff - e_cur;
+        uint32_t tw[2][VEC];
+        load_entries(p * CH, tw[0]);
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            if (i + 1 < CH)
+                load_entries(p * CH + i + 1, tw[(i + 1) & 1]);
+#pragma unroll
+            for (int e2 = 0; e2 < VEC; ++e2) {
+                const uint32_t ent = tw[i & 1][e2];
+                const float v = chunk_value<DT, ALIGNED>(buf[i], e2);
+                const float sv = __uint_as_float(__float_as_uint(v) ^ (ent & 0x80000000u));
+                lds_add_i32((ent & offmask) | region, (int32_t)ldexpf(sv, k));
+            }
+        }
+    };
+
 
     // Rows: the workgroup takes blocks of RB consecutive rows, blocks strided
     // by the grid; wave w of the workgroup takes rows w, w + waves, ... of
@@ -829,7 +894,27 @@ void hash_kernel(HashArgs a)
     load_row(bufA, clamp_row(r0));
     for (; blk < nblk; blk += (int32_t)gridDim.x) {
         const int32_t base = blk * kRowsPerBlock;
-        for (int32_t j = 0; j < per_wave; j += 2) {
+        // long rows: pieces alternate between the buffers (a.pieces is even,
+        // so every row starts in bufA); the next row's first piece is loaded
+        // during the current row's last one
+        for (int32_t j = 0; LONG && j < per_wave; ++j) {
+            const int32_t rn = j + 1 < per_wave ? r0 + a.waves : first_row(blk + (int32_t)gridDim.x);
+            for (int32_t p = 0; p < a.pieces; p += 2) {
+                load_row(bufB, clamp_row(r0), p + 1);
+                if (r0 < n32)
+                    piece(bufA, p);
+                if (p + 2 < a.pieces)
+                    load_row(bufA, clamp_row(r0), p + 2);
+                else
+                    load_row(bufA, clamp_row(rn), 0);
+                if (r0 < n32)
+                    piece(bufB, p + 1);
+            }
+            if (r0 < n32)
+                finish_row(r0, r0 - base, koff - e_cur, e_cur, mb_row, nres);
+            r0 = rn;
+        }
+        for (int32_t j = 0; !LONG && j < per_wave; j += 2) {
             const int32_t r1 = r0 + a.waves;
             load_row(bufB, clamp_row(r1));
             if (r0 < n32)
@@ -959,10 +1044,10 @@ WsLayout ws_layout(int32_t d, int32_t m)
 
 int esize(int dt) { return dt == LSH_F32 ? 4 : (dt == LSH_BF16 ? 2 : 1); }
 
-template <int FAM, int DT, bool AL, bool RC, int CH>
+template <int FAM, int DT, bool AL, bool RC, int CH, bool LONG = false>
 hipError_t launch_one(const HashArgs &a, int block, size_t lds, hipStream_t st, int64_t nblk)
 {
-    auto k = hash_kernel<FAM, DT, AL, RC, CH>;
+    auto k = hash_kernel<FAM, DT, AL, RC, CH, LONG>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess)
@@ -980,28 +1065,28 @@ hipError_t launch_one(const HashArgs &a, int block, size_t lds, hipStream_t st, 
     return hipGetLastError();
 }
 
+// Chunks per lane: aligned rows of at most 256 chunks are held whole (CH =
+// 1, 2 or 4); longer ones are read in pieces of 1024 elements (CH = 16 /
+// elements per chunk).  Unaligned rows take 8 elements per lane, whole or
+// per piece.
+template <int DT, bool AL> constexpr int long_ch() { return AL ? 16 / Elem<DT>::per16 : 8; }
+
 template <int FAM, int DT, bool AL, bool RC>
 hipError_t launch_ch(const HashArgs &a, int ch, int block, size_t lds, hipStream_t st, int64_t nblk)
 {
+    if (a.pieces > 1)
+        return launch_one<FAM, DT, AL, RC, long_ch<DT, AL>(), true>(a, block, lds, st, nblk);
     if constexpr (AL) {
         switch (ch) {
         case 1:
             return launch_one<FAM, DT, AL, RC, 1>(a, block, lds, st, nblk);
         case 2:
             return launch_one<FAM, DT, AL, RC, 2>(a, block, lds, st, nblk);
-        case 4:
-            return launch_one<FAM, DT, AL, RC, 4>(a, block, lds, st, nblk);
-        case 8:
-            return launch_one<FAM, DT, AL, RC, 8>(a, block, lds, st, nblk);
-        case 16:
-            return launch_one<FAM, DT, AL, RC, 16>(a, block, lds, st, nblk);
         default:
-            return launch_one<FAM, DT, AL, RC, 32>(a, block, lds, st, nblk);
+            return launch_one<FAM, DT, AL, RC, 4>(a, block, lds, st, nblk);
         }
     } else {
-        if (ch <= 8)
-            return launch_one<FAM, DT, AL, RC, 8>(a, block, lds, st, nblk);
-        return launch_one<FAM, DT, AL, RC, 32>(a, block, lds, st, nblk);
+        return launch_one<FAM, DT, AL, RC, 8>(a, block, lds, st, nblk);
     }
 }
 
@@ -1126,13 +1211,17 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
     // aligned, single elements otherwise)
     const int64_t nch = al ? pts->d / per16 : pts->d;
     int ch = 1;
-    while (ch < 32 && 64 * ch < nch)
+    const int ch_whole = al ? 4 : 8; // the most a lane holds of a whole row
+    while (ch < ch_whole && 64 * ch < nch)
         ch <<= 1;
-    if (!al && ch < 8)
+    if (!al)
         ch = 8;
-    if (64 * ch < nch)
-        LSH_FAIL(LSH_EINVAL, "d = %d exceeds the single-pass row size (%d elements%s)", pts->d,
-                 64 * 32 * (al ? per16 : 1), al ? "" : "; rows are not 16-byte aligned");
+    a.pieces = 1;
+    if (64 * ch < nch) { // read the row in pieces of 64 * ch chunks (an even count)
+        ch = al ? 16 / per16 : 8;
+        a.pieces = (int32_t)((nch + 64 * ch - 1) / (64 * ch));
+        a.pieces += a.pieces & 1;
+    }
 
     // LDS layout: per-wave regions of a power-of-two size (so a slot's
     // address is offset | region base), then the shared table and constants
@@ -1142,7 +1231,7 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         region <<= 1;
     a.wave_region = region;
     const int vec = al ? per16 : 1;
-    a.tab_entries = 64 * ch * vec;
+    a.tab_entries = 64 * ch * vec * a.pieces;
     const size_t lds_max = 160 * 1024;
     const int64_t nblk = (pts->n + kRowsPerBlock - 1) / kRowsPerBlock;
     const size_t masks = (size_t)((a.m + 63) / 64) * 8;

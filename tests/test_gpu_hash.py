@@ -31,8 +31,36 @@ CS_CASES = [
     (777, 960, 16, 32, "clusters"),     # d=960, m=512
     (501, 37, 5, 3, "clusters"),        # d not a multiple of 4: scalar-load path, odd m
     (1, 64, 4, 4, "clusters"),          # a single point
-    (65, 4096, 16, 64, "clusters"),     # several load groups per row
+    (65, 4096, 16, 64, "clusters"),     # long row: read in 4 pieces
+    (300, 2500, 8, 16, "clusters"),     # long row: 3 pieces, rounded up to 4
+    (257, 1301, 8, 8, "sparse"),        # long unaligned row (scalar loads, 4 pieces)
 ]
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+@pytest.mark.parametrize("d", [4096, 1301])
+def test_long_rows_growing_magnitude_recheck_exact(d, family):
+    """Long rows whose magnitude grows along the row: every later piece raises
+    the exponent, so the bins are shifted several times per row.  The FP64
+    recheck must still reproduce the oracle exactly, and without it the
+    projection stays within 1e-5 * ||x||.  (The codes of the fast path are
+    the FP32 evaluation: with |sqrt(m) y| near 1e6 its rounding exceeds the
+    oracle's fixed 1e-4 * w near-edge band, so they are not compared.)"""
+    dev()
+    n, K, L = 400, 16, 32
+    g = np.random.default_rng(5)
+    x = (g.standard_normal((n, d)) * np.exp2(np.arange(d) // 1024 * 5.0)).astype(np.float32)
+    h, s = synth.cs_state(d, K * L, 6)
+    b = synth.shifts(K * L, 4.0, 6)
+    x64 = x.astype(np.float64)
+    ref = oracle.hash_points(x64, family, K, L, kind="cs", w=4.0, b=b, h=h, s=s)
+    kw = dict(family=family, K=K, L=L, w=4.0, b=to_dev(b), codes=True)
+    cnt = to_dev(np.zeros(4, np.uint64))
+    out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), recheck=True, counters=cnt, **kw)
+    compare_hash(out, ref, x64, K, L, exact=True, what=f"growing d={d} recheck")
+    kw.update(codes=False, keys=False)
+    out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), proj=True, **kw)
+    compare_hash(out, ref, x64, K, L, what=f"growing d={d}")
 
 
 @pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
