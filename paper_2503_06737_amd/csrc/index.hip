@@ -5,19 +5,24 @@
 // run heads.  Keys are 64-bit digests (E2LSH) or K sign bits (SRP), so the
 // order is built most-significant-digit first:
 //   1. mask    - OR and AND of every key of a table: the bits that vary;
+//                the same pass counts the top B key bits per tile, a guess
+//                that holds when the top bit varies (digests), and tables
+//                where it does not are counted again;
 //   2. msd     - the top B varying bits (B grows with n, at most 10) form the
 //                segment digit: per-tile digit counts, their scan (segment
-//                starts) and a stable scatter of (key, id) into 2^B segments
-//                per table;
-//   3. segment - one 512-thread workgroup per segment of at most 4096 keys
-//                sorts it in LDS: 16-bit index arrays ranked by the segment's
-//                varying 8-bit chunks, least significant first (only the top
-//                four when more vary, unless an adjacent pair shows two
-//                distinct keys that agree on them);
-//   4. big     - one 1024-thread workgroup per larger segment (heavy buckets,
-//                skewed digits) splits it recursively by its own top varying
-//                byte in global memory: parts holding a single key are
-//                copied, parts of at most 8192 keys are sorted in LDS;
+//                starts, and the list of segments too large for step 3) and
+//                a stable scatter of (key, id) into 2^B segments per table;
+//   3. segment - one workgroup per segment of at most 4096 keys (256 threads
+//                up to 2048 keys, else 512) sorts it in LDS: 16-bit index
+//                arrays ranked by the segment's varying 8-bit chunks, least
+//                significant first (only the top three when more vary, unless
+//                an adjacent pair shows two distinct keys that agree on them);
+//   4. big     - larger segments (heavy buckets, skewed digits): a sampled
+//                pivot key splits each in parallel over tiles into less /
+//                equal / greater parts; then one 1024-thread workgroup per
+//                segment splits the rest recursively (pivot or top varying
+//                byte): parts holding a single key are copied, parts of at
+//                most 8192 keys are sorted in LDS;
 //   5. heads   - run heads are counted per tile, scanned per table, and the
 //                distinct keys and bucket start offsets are written.
 // Every scatter ranks keys stably (one ballot per digit bit gives the lanes
@@ -36,6 +41,10 @@ constexpr int kMsdRadixMax = 1 << kMsdBitsMax;
 constexpr int kRadix = 256;                // 8-bit digits below the segment digit
 constexpr int kSegThreads = 512;
 constexpr int kSegSmall = kSegThreads * kItems; // 4096: segments sorted by kSegThreads
+// segments of at most 2048 keys take a 256-thread workgroup with half the
+// LDS, so that four of them share a CU (two of the 4096-key ones fit)
+constexpr int kSegThreadsS = 256;
+constexpr int kSegTiny = kSegThreadsS * kItems; // 2048
 constexpr int kSegLarge = kThreads * kItems;    // 8192: parts sorted inside the big path
 constexpr int kChunks = 8;     // 8-bit chunks of a key (a segment's varying bits lie below its digit)
 constexpr int kFastChunks = 3; // chunks sorted before the adjacent-pair check
@@ -189,24 +198,41 @@ __device__ __forceinline__ void block_or_and(const uint64_t *keys, int64_t cnt, 
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kThreads) void mask_kernel(BuildArgs a)
+// OR / AND of every key of a table and, guessing that the table's top key
+// bit varies (true of 64-bit digests), the tile's counts of the segment
+// digit key >> (64 - B).  msd_reset / msd_up recount the tables where the
+// guess fails (short SRP keys).
+__global__ __launch_bounds__(kThreads) void mask_up_kernel(BuildArgs a)
 {
     const int t = blockIdx.y;
+    const int R = 1 << a.msd_bits;
+    const int shift = 64 - a.msd_bits;
+    __shared__ uint32_t h[kMsdRadixMax];
+    __shared__ uint64_t so[kWaves], sa[kWaves];
+    for (int i = threadIdx.x; i < R; i += kThreads)
+        h[i] = 0;
+    __syncthreads();
     const uint64_t *k = a.kin + (int64_t)t * a.key_ld;
     const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint64_t v[kItems];
+    const bool full = base + kTile <= a.n;
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t i = base + it * kThreads + threadIdx.x;
+        v[it] = full || i < a.n ? k[i] : 0;
+    }
     uint64_t vo = 0, va = ~0ull;
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int64_t i = base + it * kThreads + threadIdx.x;
-        if (i < a.n) {
-            const uint64_t v = k[i];
-            vo |= v;
-            va &= v;
+        if (full || i < a.n) {
+            vo |= v[it];
+            va &= v[it];
+            atomicAdd(&h[(uint32_t)(v[it] >> shift)], 1u);
         }
     }
     vo = wave_or64(vo);
     va = wave_and64(va);
-    __shared__ uint64_t so[kWaves], sa[kWaves];
     const int wid = threadIdx.x / kWave;
     if (lane_id() == 0) {
         so[wid] = vo;
@@ -221,13 +247,37 @@ __global__ __launch_bounds__(kThreads) void mask_kernel(BuildArgs a)
         atomicOr((unsigned long long *)&a.tor[t], (unsigned long long)so[0]);
         atomicAnd((unsigned long long *)&a.tand[t], (unsigned long long)sa[0]);
     }
+    uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
+    for (int i = threadIdx.x; i < R; i += kThreads) {
+        th[i] = h[i];
+        if (h[i])
+            atomicAdd(&a.ghist[(t << a.msd_bits) + i], h[i]);
+    }
 }
 
 // ------------------------------------------------------------ segment digit
 
+__device__ __forceinline__ bool guess_holds(const BuildArgs &a, int t)
+{
+    return top_shift(a.tor[t] & ~a.tand[t], a.msd_bits) == 64 - a.msd_bits;
+}
+
+// Tables whose top key bit does not vary: clear the guessed segment sizes.
+__global__ __launch_bounds__(kMsdRadixMax) void msd_reset_kernel(BuildArgs a)
+{
+    const int t = blockIdx.x;
+    if (guess_holds(a, t) || (int)threadIdx.x >= (1 << a.msd_bits))
+        return;
+    a.ghist[(t << a.msd_bits) + threadIdx.x] = 0;
+}
+
+// Tables whose top key bit does not vary: count the segment digit (the top
+// B varying bits) per tile.
 __global__ __launch_bounds__(kThreads) void msd_up_kernel(BuildArgs a)
 {
     const int t = blockIdx.y;
+    if (guess_holds(a, t))
+        return;
     const int R = 1 << a.msd_bits;
     __shared__ uint32_t h[kMsdRadixMax];
     for (int i = threadIdx.x; i < R; i += blockDim.x)
@@ -252,20 +302,58 @@ __global__ __launch_bounds__(kThreads) void msd_up_kernel(BuildArgs a)
 }
 
 // tile_hist[t][tile][d] <- global start of the tile's run of digit d;
-// seg_start[t][d] <- start of segment d.
+// seg_start[t][d] <- start of segment d.  Segments larger than an LDS sort
+// join the big list (blist, btile) in a range the table reserves with one
+// atomic add per list; the order of the tables in the lists does not matter
+// (every big segment is sorted on its own).
 __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
 {
     const int t = blockIdx.x;
     const int R = 1 << a.msd_bits;
     __shared__ uint32_t wsum[kMsdRadixMax / kWave];
+    __shared__ uint32_t bres[2];
     const int d = threadIdx.x;
     const uint32_t c = d < R ? a.ghist[(t << a.msd_bits) + d] : 0u;
     uint32_t run = scan_excl(c, R, wsum);
+    const bool big = d < R && c > (uint32_t)kSegSmall;
+    const uint32_t ntl = big ? (c + kTile - 1) / kTile : 0u;
+    const uint32_t bi = scan_excl(big ? 1u : 0u, R, wsum);
+    const uint32_t ti = scan_excl(ntl, R, wsum);
+    if (d == R - 1) {
+        bres[0] = atomicAdd(&a.bcount[0], bi + (big ? 1u : 0u));
+        bres[1] = atomicAdd(&a.bcount[2], ti + ntl);
+    }
+    __syncthreads();
+    if (big) {
+        const uint32_t b0 = bres[0] + bi, t0 = bres[1] + ti;
+        uint32_t *b = a.blist + kBig * b0;
+        b[0] = (uint32_t)t;
+        b[1] = (uint32_t)d;
+        b[2] = t0;
+        b[3] = ntl;
+        b[4] = 0;
+        for (uint32_t k = 0; k < ntl; ++k) {
+            a.btile[2 * (t0 + k)] = b0;
+            a.btile[2 * (t0 + k) + 1] = k;
+        }
+    }
     if (d >= R)
         return;
     a.seg_start[(t << a.msd_bits) + d] = run;
     uint32_t *th = a.tile_hist + (int64_t)t * a.ntiles * R + d;
-    for (int tile = 0; tile < a.ntiles; ++tile) {
+    int tile = 0;
+    for (; tile + 8 <= a.ntiles; tile += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = th[(int64_t)(tile + u) * R];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            th[(int64_t)(tile + u) * R] = run;
+            run += v[u];
+        }
+    }
+    for (; tile < a.ntiles; ++tile) {
         const uint32_t v = th[(int64_t)tile * R];
         th[(int64_t)tile * R] = run;
         run += v;
@@ -274,23 +362,93 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
 
 // ------------------------------------------------------- stable tile scatter
 
+// The lanes of the wave whose NB-bit digit equals this lane's digit dg (bits
+// of dg at NB and above must be zero): one ballot per bit, each kept where
+// this lane's bit agrees.  With m the bit sign-extended (0 or all ones), a
+// half of the mask is updated as half & ~(ballot half ^ m): one three-input
+// bit operation (truth table 0x90 over (half, ballot half, m)).  Four bits
+// at a time: their four compares first, then two wait states before a
+// compare result is read by a vector instruction.
+template <int B0>
+__device__ __forceinline__ void match_4bits(uint32_t dg, uint32_t &lo, uint32_t &hi)
+{
+    uint32_t m0, m1, m2, m3;
+    uint64_t s0, s1, s2, s3;
+    asm volatile("v_bfe_i32 %[m0], %[dg], %[b0], 1\n\t"
+                 "v_bfe_i32 %[m1], %[dg], %[b1], 1\n\t"
+                 "v_bfe_i32 %[m2], %[dg], %[b2], 1\n\t"
+                 "v_bfe_i32 %[m3], %[dg], %[b3], 1\n\t"
+                 "v_cmp_ne_u32_e64 %[s0], 0, %[m0]\n\t"
+                 "v_cmp_ne_u32_e64 %[s1], 0, %[m1]\n\t"
+                 "v_cmp_ne_u32_e64 %[s2], 0, %[m2]\n\t"
+                 "v_cmp_ne_u32_e64 %[s3], 0, %[m3]"
+                 : [m0] "=&v"(m0), [m1] "=&v"(m1), [m2] "=&v"(m2), [m3] "=&v"(m3),
+                   [s0] "=&s"(s0), [s1] "=&s"(s1), [s2] "=&s"(s2), [s3] "=&s"(s3)
+                 : [dg] "v"(dg), [b0] "n"(B0), [b1] "n"(B0 + 1), [b2] "n"(B0 + 2),
+                   [b3] "n"(B0 + 3));
+    asm volatile("s_nop 1\n\t"
+                 "v_bitop3_b32 %[lo], %[lo], %[a0], %[m0] bitop3:0x90\n\t"
+                 "v_bitop3_b32 %[hi], %[hi], %[c0], %[m0] bitop3:0x90\n\t"
+                 "v_bitop3_b32 %[lo], %[lo], %[a1], %[m1] bitop3:0x90\n\t"
+                 "v_bitop3_b32 %[hi], %[hi], %[c1], %[m1] bitop3:0x90\n\t"
+                 "v_bitop3_b32 %[lo], %[lo], %[a2], %[m2] bitop3:0x90\n\t"
+                 "v_bitop3_b32 %[hi], %[hi], %[c2], %[m2] bitop3:0x90\n\t"
+                 "v_bitop3_b32 %[lo], %[lo], %[a3], %[m3] bitop3:0x90\n\t"
+                 "v_bitop3_b32 %[hi], %[hi], %[c3], %[m3] bitop3:0x90"
+                 : [lo] "+v"(lo), [hi] "+v"(hi)
+                 : [m0] "v"(m0), [m1] "v"(m1), [m2] "v"(m2), [m3] "v"(m3),
+                   [a0] "s"((uint32_t)s0), [c0] "s"((uint32_t)(s0 >> 32)),
+                   [a1] "s"((uint32_t)s1), [c1] "s"((uint32_t)(s1 >> 32)),
+                   [a2] "s"((uint32_t)s2), [c2] "s"((uint32_t)(s2 >> 32)),
+                   [a3] "s"((uint32_t)s3), [c3] "s"((uint32_t)(s3 >> 32)));
+}
+
+template <int NB>
+__device__ __forceinline__ void match_digit(uint32_t dg, uint32_t &lo, uint32_t &hi)
+{
+    static_assert(NB == 8 || NB == 10, "digit widths used here");
+    lo = ~0u;
+    hi = ~0u;
+    match_4bits<0>(dg, lo, hi);
+    match_4bits<4>(dg, lo, hi);
+    if constexpr (NB == 10) {
+        // the last two bits in C: the compiler fuses them the same way
+#pragma unroll
+        for (int b = 8; b < 10; ++b) {
+            const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)dg, b, 1);
+            const uint64_t bal = __ballot(m != 0u);
+            lo &= ~((uint32_t)bal ^ m);
+            hi &= ~((uint32_t)(bal >> 32) ^ m);
+        }
+    }
+}
+
+// Lanes below this one in a 64-lane mask given as two halves.
+__device__ __forceinline__ uint32_t count_below(uint32_t lo, uint32_t hi)
+{
+    return __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+}
+
 template <int RMAX> struct ScatterLds {
-    uint64_t key[kTile];
-    uint32_t id[kTile];
-    uint16_t whist[kWaves][RMAX]; // per-wave digit counts (at most 512)
-    uint32_t lbase[RMAX];
+    // per-wave digit counts (a wave ranks at most 512 keys), then per-wave
+    // prefixes inside each digit (at most 8192)
+    alignas(4) uint16_t whist[kWaves][RMAX];
+    uint32_t lbase[RMAX];   // first sorted position of each digit in the tile
+    uint32_t goff[RMAX];    // the caller's output offset of each digit
     uint32_t wsum[RMAX / kWave];
-    uint32_t count[RMAX]; // the tile's count of each digit (for the caller)
+    uint32_t count[RMAX];   // the tile's count of each digit (for the caller)
+    uint16_t perm[kTile];   // tile position of the key at each sorted position
 };
 
 // Stable scatter of one tile (1024 threads): keys (and ids, or id0 + i when
 // ids is NULL) [0, cnt) go to kout/iout at goff[digit] + (rank among the
 // tile's keys of that digit), digit = (key >> shift) & (2^bits - 1).  Wave w
 // ranks rows w*8 .. w*8+7 of 64 keys; the lanes holding the same digit come
-// from one ballot per digit bit.  The tile is reordered in LDS and written
-// as contiguous digit runs.  On return s.count[d] holds the tile's count of
-// digit d.
-template <int RMAX>
+// from one ballot per digit bit.  Only the order is kept in LDS (the tile
+// position of each sorted position); the keys are read again (from cache)
+// in that order and written as contiguous digit runs, so two tiles fit in
+// a CU's LDS.  On return s.count[d] holds the tile's count of digit d.
+template <int RMAX, int RLOG = __builtin_ctz(RMAX)>
 __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t *kin,
                                              const uint32_t *iin, uint32_t id0, int cnt,
                                              int shift, int bits, const uint32_t *goff,
@@ -299,58 +457,59 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
     const int R = 1 << bits;
     const uint32_t dmask = (uint32_t)R - 1u;
     const int tid = threadIdx.x, wid = tid / kWave, lane = lane_id();
-    for (int i = tid; i < kWaves * RMAX; i += kThreads)
-        (&s.whist[0][0])[i] = 0;
+    for (int i = tid; i < kWaves * RMAX / 2; i += kThreads)
+        ((uint32_t *)&s.whist[0][0])[i] = 0u;
+    for (int i = tid; i < R; i += kThreads)
+        s.goff[i] = goff[i];
     __syncthreads();
 
     const int wbase = wid * (kWave * kItems);
-    uint64_t key[kItems];
-    uint32_t id[kItems], rank[kItems], dg[kItems];
+    uint32_t rank[kItems], dg[kItems];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int i = wbase + it * kWave + lane;
-        if (i < cnt) {
-            key[it] = kin[i];
-            id[it] = iin ? iin[i] : id0 + (uint32_t)i;
-            dg[it] = (uint32_t)(key[it] >> shift) & dmask;
-        } else {
-            // positions past the end rank after every real key of the last
-            // digit (they come last in the ranking order); never written
-            key[it] = 0;
-            id[it] = 0xffffffffu;
-            dg[it] = dmask;
-        }
+        // positions past the end rank after every real key of the last
+        // digit (they come last in the ranking order); never written
+        dg[it] = i < cnt ? (uint32_t)(kin[i] >> shift) & dmask : dmask;
     }
-    const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-        uint64_t peers = ~0ull;
-        for (int b = 0; b < bits; ++b) {
-            const uint64_t bal = __ballot((dg[it] >> b) & 1u);
-            peers &= ((dg[it] >> b) & 1u) ? bal : ~bal;
-        }
-        const uint32_t before = __popcll(peers & lt);
-        const uint32_t old = s.whist[wid][dg[it]];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        // digit bits at `bits` and above are zero: their ballots keep every lane
+        uint32_t plo, phi;
+        match_digit<RLOG>(dg[it], plo, phi);
+        const uint32_t before = count_below(plo, phi);
+        const uint32_t npeer = __popc(plo) + __popc(phi);
+        // the first lane of each digit adds the row's count to its 16-bit
+        // counter (half of a 32-bit word; a wave counts at most 512 keys, so
+        // no carry crosses into the other half); every lane then reads the
+        // count including this row.  A wave's LDS operations run in order.
         if (before == 0)
-            s.whist[wid][dg[it]] = (uint16_t)(old + __popcll(peers));
+            __hip_atomic_fetch_add((uint32_t *)__builtin_assume_aligned(
+                                       &s.whist[wid][dg[it] & ~1u], 4),
+                                   npeer << (16u * (dg[it] & 1u)), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        rank[it] = old + before;
+        rank[it] = (uint32_t)s.whist[wid][dg[it]] + before - npeer;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     // per digit: exclusive scan over waves; then over digits
     uint32_t tot = 0;
     if (tid < R) {
-        uint32_t c[kWaves];
+        // eight waves at a time (register budget)
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w)
-            c[w] = s.whist[w][tid];
+        for (int w0 = 0; w0 < kWaves; w0 += 8) {
+            uint32_t c[8];
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            s.whist[w][tid] = (uint16_t)tot; // prefix within the tile: < 8192
-            tot += c[w];
+            for (int w = 0; w < 8; ++w)
+                c[w] = s.whist[w0 + w][tid];
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                s.whist[w0 + w][tid] = (uint16_t)tot; // prefix within the tile: < 8192
+                tot += c[w];
+            }
         }
     }
     const uint32_t excl = scan_excl(tot, R, s.wsum);
@@ -359,22 +518,20 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-        const uint32_t pos = s.lbase[dg[it]] + s.whist[wid][dg[it]] + rank[it];
-        s.key[pos] = key[it];
-        s.id[pos] = id[it];
+        const int i = wbase + it * kWave + lane;
+        if (i < cnt)
+            s.perm[s.lbase[dg[it]] + s.whist[wid][dg[it]] + rank[it]] = (uint16_t)i;
     }
     __syncthreads();
-    for (int q = tid; q < kTile; q += kThreads) {
-        const uint32_t idv = s.id[q];
-        if (idv == 0xffffffffu)
-            continue;
-        const uint64_t k = s.key[q];
+    // the real keys hold sorted positions [0, cnt): padding ranks last
+    for (int q = tid; q < cnt; q += kThreads) {
+        const uint32_t i = s.perm[q];
+        const uint64_t k = kin[i];
         const uint32_t d = (uint32_t)(k >> shift) & dmask;
-        const uint32_t g = goff[d] + ((uint32_t)q - s.lbase[d]);
+        const uint32_t g = s.goff[d] + ((uint32_t)q - s.lbase[d]);
         kout[g] = k;
-        iout[g] = idv;
+        iout[g] = iin ? iin[i] : id0 + i;
     }
-    __syncthreads();
     // tile digit counts for the caller (lbase is exclusive, so count = next - this)
     if (tid < R) {
         // the last digit also holds the padding, which ranks after its keys
@@ -384,7 +541,9 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kThreads) void msd_scatter_kernel(BuildArgs a)
+// two workgroups per CU: at most 64 VGPRs (eight waves per SIMD)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void
+msd_scatter_kernel(BuildArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     ScatterLds<kMsdRadixMax> &s = *(ScatterLds<kMsdRadixMax> *)lds;
@@ -403,82 +562,139 @@ __global__ __launch_bounds__(kThreads) void msd_scatter_kernel(BuildArgs a)
 
 template <int NT> struct SegLds {
     static constexpr int S = NT * kItems;
+    static constexpr int NW = NT / kWave;
     uint64_t key[S];
     uint32_t id[S];
     uint16_t ix[2][S];
-    uint32_t whist[NT / kWave][kRadix];
-    uint32_t lbase[kRadix];
-    uint32_t wsum[kRadix / kWave];
-    uint64_t so[NT / kWave], sa[NT / kWave];
+    // per-wave digit counts (a wave ranks at most 512 keys), two buffers
+    // used by alternate passes: a pass clears the other one for the next
+    alignas(8) uint16_t whist[2][NW][kRadix];
+    alignas(8) uint16_t base[NW][kRadix]; // per wave: its first position of each digit
+    uint64_t so[NW], sa[NW];
     int flag;
 };
 
+// Inclusive sum over the lanes of a wave: shifts within rows of 16 lanes,
+// then the last lane of a row broadcast to the rows above it.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true); // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true); // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true); // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true); // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false); // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); // row_bcast:31
+    return x;
+}
+
 // One stable counting pass of the index array src -> dst by chunk p of the
-// keys.  Wave w ranks positions [w*rows*64, (w+1)*rows*64), row by row.
+// keys, with digit counts in s.whist[buf] (zero on entry; s.whist[buf ^ 1]
+// is zero on return).  Wave w ranks positions [w*rows*64, (w+1)*rows*64),
+// row by row.  Two workgroup barriers: after the counts, after the scatter.
 template <int NT>
 __device__ __forceinline__ void seg_rank_pass(SegLds<NT> &s, const uint16_t *src, uint16_t *dst,
-                                              int cnt, int rows, int p)
+                                              int cnt, int rows, int p, int buf)
 {
     constexpr int NW = NT / kWave;
     const int tid = threadIdx.x, wid = tid / kWave, lane = lane_id();
-    for (int i = tid; i < NW * kRadix; i += NT)
-        (&s.whist[0][0])[i] = 0;
-    __syncthreads();
-    const uint64_t lt = lanemask_lt();
-    uint32_t dgs[kItems], rank[kItems];
-    uint16_t ixs[kItems];
+    uint16_t (*wh)[kRadix] = s.whist[buf];
+    // The other buffer's last readers (the previous pass's digit scan)
+    // finished before the barrier that ended that pass; its next writers
+    // (the next pass's ranking) start after this pass's last barrier.
+    {
+        uint32_t *z = (uint32_t *)s.whist[buf ^ 1][wid];
+        z[lane] = 0u;
+        z[lane + kWave] = 0u;
+    }
+    uint32_t ixs[kItems], dgs[kItems], rank[kItems];
     const int wbase = wid * rows * kWave;
+    // All of this wave's indices, then all of their digits (byte p of the
+    // key, read as a byte), with no branch between the loads so that their
+    // latencies overlap.  j < NW * rows * 64 <= NT * kItems for every item,
+    // also for the items at and past `rows` (which are loaded and ignored).
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-        if (it < rows) {
-            const int j = wbase + it * kWave + lane;
-            const bool valid = j < cnt;
-            const uint16_t ix = valid ? src[j] : 0;
-            // positions past the end take digit 255 and rank after every
-            // real key (they come last in the ranking order); never stored
-            const uint32_t dg = valid ? (uint32_t)(s.key[ix] >> (8 * p)) & 255u : 255u;
-            uint64_t peers = ~0ull;
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const uint64_t bal = __ballot((dg >> b) & 1u);
-                peers &= ((dg >> b) & 1u) ? bal : ~bal;
-            }
-            const uint32_t before = __popcll(peers & lt);
-            const uint32_t old = s.whist[wid][dg];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (before == 0)
-                s.whist[wid][dg] = old + __popcll(peers);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            rank[it] = old + before;
-            dgs[it] = dg;
-            ixs[it] = ix;
-        }
+        const int j = wbase + it * kWave + lane;
+        const uint32_t ix = src[j];
+        ixs[it] = j < cnt ? ix : 0u;
     }
-    __syncthreads();
-    uint32_t tot = 0;
-    if (tid < kRadix) {
-        uint32_t c[NW];
+    const uint8_t *kbytes = (const uint8_t *)s.key + p;
 #pragma unroll
-        for (int w = 0; w < NW; ++w)
-            c[w] = s.whist[w][tid];
+    for (int it = 0; it < kItems; ++it) {
+        const int j = wbase + it * kWave + lane;
+        // positions past the end take digit 255 and rank after every real
+        // key (they come last in the ranking order); never stored
+        const uint32_t dg = kbytes[8 * ixs[it]];
+        dgs[it] = j < cnt ? dg : 255u;
+    }
+    // Row by row, the first lane of each digit adds the row's count of it to
+    // the digit's 16-bit counter (half of a 32-bit word; at most 512, so no
+    // carry crosses into the other half); every lane then reads the count
+    // including this row (rank = that count + lanes of the digit below it -
+    // lanes of the digit in the row).  A wave's LDS operations run in order,
+    // so no wait is needed between rows; the reads are made for every item
+    // (past `rows` too, and ignored) so that none sits in a branch and they
+    // complete together.
+    int adj[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        adj[it] = 0;
+        if (it < rows) {
+            uint32_t plo, phi;
+            match_digit<8>(dgs[it], plo, phi);
+            const uint32_t before = count_below(plo, phi);
+            const uint32_t npeer = __popc(plo) + __popc(phi);
+            if (before == 0)
+                __hip_atomic_fetch_add(
+                    (uint32_t *)__builtin_assume_aligned(&wh[wid][dgs[it] & ~1u], 4),
+                    npeer << (16u * (dgs[it] & 1u)), __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_WAVEFRONT);
+            adj[it] = (int)before - (int)npeer;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        rank[it] = wh[wid][dgs[it]];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int it = 0; it < kItems; ++it)
+        rank[it] += (uint32_t)adj[it];
+    __syncthreads();
+    // Every wave scans the 256 digit totals itself (lane l: digits 4l ..
+    // 4l+3) and writes its own first position of each digit: digit start +
+    // the digit's count in the waves before it.  Only this wave reads its
+    // row of s.base back, so no barrier is needed before the scatter.
+    {
+        uint32_t c[4] = {0u, 0u, 0u, 0u}, pre[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            s.whist[w][tid] = tot;
-            tot += c[w];
+            const uint64_t v = *(const uint64_t *)&wh[w][4 * lane];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t x = (uint32_t)(v >> (16 * k)) & 0xffffu;
+                c[k] += x;
+                pre[k] += w < wid ? x : 0u;
+            }
         }
+        const uint32_t tot = c[0] + c[1] + c[2] + c[3];
+        uint32_t e = wave_incl_scan(tot) - tot;
+        uint64_t out = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            out |= (uint64_t)(e + pre[k]) << (16 * k);
+            e += c[k];
+        }
+        *(uint64_t *)&s.base[wid][4 * lane] = out;
     }
-    const uint32_t excl = scan_excl(tot, kRadix, s.wsum);
-    if (tid < kRadix)
-        s.lbase[tid] = excl;
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         if (it < rows) {
             const int j = wbase + it * kWave + lane;
             if (j < cnt)
-                dst[s.lbase[dgs[it]] + s.whist[wid][dgs[it]] + rank[it]] = ixs[it];
+                dst[s.base[wid][dgs[it]] + rank[it]] = (uint16_t)ixs[it];
         }
     }
     __syncthreads();
@@ -522,6 +738,8 @@ __device__ void seg_sort_body(SegLds<NT> &s, const uint64_t *kin, const uint32_t
     }
     if (tid == 0)
         s.flag = 0;
+    for (int i = tid; i < (int)(sizeof(s.whist) / 4); i += NT)
+        ((uint32_t *)s.whist)[i] = 0u;
     __syncthreads();
     vo = 0;
     va = ~0ull;
@@ -538,10 +756,10 @@ __device__ void seg_sort_body(SegLds<NT> &s, const uint64_t *kin, const uint32_t
         fast &= fast - 1;
     const int rows = (cnt + NT - 1) / NT;
 
-    int cur = 0;
+    int cur = 0, npass = 0;
     for (int p = 0; p < kChunks; ++p) {
         if ((fast >> p) & 1u) {
-            seg_rank_pass<NT>(s, s.ix[cur], s.ix[cur ^ 1], cnt, rows, p);
+            seg_rank_pass<NT>(s, s.ix[cur], s.ix[cur ^ 1], cnt, rows, p, npass++ & 1);
             cur ^= 1;
         }
     }
@@ -564,7 +782,7 @@ __device__ void seg_sort_body(SegLds<NT> &s, const uint64_t *kin, const uint32_t
             cur = 0;
             for (int p = 0; p < kChunks; ++p) {
                 if ((all >> p) & 1u) {
-                    seg_rank_pass<NT>(s, s.ix[cur], s.ix[cur ^ 1], cnt, rows, p);
+                    seg_rank_pass<NT>(s, s.ix[cur], s.ix[cur ^ 1], cnt, rows, p, npass++ & 1);
                     cur ^= 1;
                 }
             }
@@ -578,75 +796,25 @@ __device__ void seg_sort_body(SegLds<NT> &s, const uint64_t *kin, const uint32_t
     __syncthreads();
 }
 
-// Segment d of table t (blockIdx = (d, t)) when it holds 1..kSegSmall keys.
-__global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(BuildArgs a)
+// Segment d of table t (blockIdx = (d, t)) when it holds LO+1 .. NT*kItems
+// keys.
+template <int NT, int LO>
+__global__ __launch_bounds__(NT) void seg_sort_kernel(BuildArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    SegLds<kSegThreads> &s = *(SegLds<kSegThreads> *)lds;
+    SegLds<NT> &s = *(SegLds<NT> *)lds;
     const int d = blockIdx.x, t = blockIdx.y;
     if (d >= (1 << a.msd_bits))
         return;
     const int e = (t << a.msd_bits) + d;
     const int cnt = (int)a.ghist[e];
-    if (cnt == 0 || cnt > kSegSmall)
+    if (cnt <= LO || cnt > NT * kItems)
         return;
     const int64_t base = (int64_t)t * a.n + a.seg_start[e];
-    seg_sort_body<kSegThreads>(s, a.ka + base, a.ia + base, cnt, a.kb + base, a.ids + base);
+    seg_sort_body<NT>(s, a.ka + base, a.ia + base, cnt, a.kb + base, a.ids + base);
 }
 
 // --------------------------------------------------------- big segments
-
-// One workgroup lists the segments larger than kSegSmall and their tiles.
-__global__ __launch_bounds__(kThreads) void big_plan_kernel(BuildArgs a)
-{
-    __shared__ uint32_t part[kThreads], tpart[kThreads];
-    const int tid = threadIdx.x;
-    const int nseg = a.L << a.msd_bits;
-    const int per = (nseg + kThreads - 1) / kThreads;
-    const int lo = tid * per, hi = min(nseg, lo + per);
-    uint32_t nb = 0, nt = 0;
-    for (int e = lo; e < hi; ++e) {
-        const uint32_t c = a.ghist[e];
-        if (c > (uint32_t)kSegSmall) {
-            ++nb;
-            nt += (c + kTile - 1) / kTile;
-        }
-    }
-    part[tid] = nb;
-    tpart[tid] = nt;
-    __syncthreads();
-    for (int o = 1; o < kThreads; o <<= 1) {
-        const uint32_t u = tid >= o ? part[tid - o] : 0;
-        const uint32_t v = tid >= o ? tpart[tid - o] : 0;
-        __syncthreads();
-        part[tid] += u;
-        tpart[tid] += v;
-        __syncthreads();
-    }
-    uint32_t bi = part[tid] - nb, ti = tpart[tid] - nt;
-    for (int e = lo; e < hi; ++e) {
-        const uint32_t c = a.ghist[e];
-        if (c > (uint32_t)kSegSmall) {
-            const uint32_t ntl = (c + kTile - 1) / kTile;
-            uint32_t *b = a.blist + kBig * bi;
-            b[0] = (uint32_t)(e >> a.msd_bits);
-            b[1] = (uint32_t)(e & ((1 << a.msd_bits) - 1));
-            b[2] = ti;
-            b[3] = ntl;
-            b[4] = 0;
-            for (uint32_t k = 0; k < ntl; ++k) {
-                a.btile[2 * (ti + k)] = bi;
-                a.btile[2 * (ti + k) + 1] = k;
-            }
-            ++bi;
-            ti += ntl;
-        }
-    }
-    if (tid == kThreads - 1) {
-        a.bcount[0] = part[tid];
-        a.bcount[2] = tpart[tid];
-    }
-}
 
 // A key that fills at least 16 of 64 evenly spaced samples of keys[0, size)
 // (wave 0 of the block decides; lowest lane on ties).  Returns the count
@@ -866,6 +1034,11 @@ struct BigLds {
     uint32_t pivot_cnt;
     int top;
 };
+
+constexpr size_t kLdsBytes = 160 * 1024; // per CU
+static_assert(sizeof(BigLds) <= kLdsBytes, "big-segment workgroup exceeds the LDS");
+static_assert(4 * sizeof(SegLds<kSegThreadsS>) <= kLdsBytes, "four small sorts per CU");
+static_assert(2 * sizeof(SegLds<kSegThreads>) <= kLdsBytes, "two segment sorts per CU");
 
 // The big path calls these out of line: inlined together with the
 // partition they exceed the register budget of a 1024-thread workgroup.
@@ -1267,13 +1440,13 @@ struct WsLayout {
     int ntiles, nhtiles, bits, big_grid, maxbt;
 };
 
-// Segment digit width: about 2048 keys per segment (a workgroup per
+// Segment digit width: about 1024 keys per segment (a workgroup per
 // segment has a fixed cost, so segments are not made smaller than that), at
 // most 2^10 segments.
 int msd_bits_for(int64_t n)
 {
     int b = 1;
-    while (b < lsh::kMsdBitsMax && ((int64_t)2048 << b) < n)
+    while (b < lsh::kMsdBitsMax && ((int64_t)1024 << b) < n)
         ++b;
     return b;
 }
@@ -1415,14 +1588,18 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
 
     const size_t scatter_lds = sizeof(ScatterLds<kMsdRadixMax>);
     const size_t seg_lds = sizeof(SegLds<kSegThreads>);
+    const size_t segs_lds = sizeof(SegLds<kSegThreadsS>);
+    const void *seg_fn = (const void *)seg_sort_kernel<kSegThreads, kSegTiny>;
+    const void *segs_fn = (const void *)seg_sort_kernel<kSegThreadsS, 0>;
     const size_t big_lds = sizeof(BigLds);
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)msd_scatter_kernel,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)scatter_lds)) !=
             hipSuccess ||
-        (e = hipFuncSetAttribute((const void *)seg_sort_kernel,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)seg_lds)) !=
-            hipSuccess ||
+        (e = hipFuncSetAttribute(seg_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)seg_lds)) != hipSuccess ||
+        (e = hipFuncSetAttribute(segs_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)segs_lds)) != hipSuccess ||
         (e = hipFuncSetAttribute((const void *)big_sort_kernel,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)big_lds)) !=
             hipSuccess)
@@ -1431,12 +1608,15 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     const int nseg = L << wl.bits;
     dim3 tiles(wl.ntiles, L);
     hipLaunchKernelGGL(build_init_kernel, dim3((nseg + 255) / 256), dim3(256), 0, s, ba);
-    hipLaunchKernelGGL(mask_kernel, tiles, dim3(kThreads), 0, s, ba);
+    hipLaunchKernelGGL(mask_up_kernel, tiles, dim3(kThreads), 0, s, ba);
+    hipLaunchKernelGGL(msd_reset_kernel, dim3(L), dim3(kMsdRadixMax), 0, s, ba);
     hipLaunchKernelGGL(msd_up_kernel, tiles, dim3(kThreads), 0, s, ba);
     hipLaunchKernelGGL(msd_scan_kernel, dim3(L), dim3(kMsdRadixMax), 0, s, ba);
     hipLaunchKernelGGL(msd_scatter_kernel, tiles, dim3(kThreads), scatter_lds, s, ba);
-    hipLaunchKernelGGL(seg_sort_kernel, dim3(1 << wl.bits, L), dim3(kSegThreads), seg_lds, s, ba);
-    hipLaunchKernelGGL(big_plan_kernel, dim3(1), dim3(kThreads), 0, s, ba);
+    hipLaunchKernelGGL((seg_sort_kernel<kSegThreadsS, 0>), dim3(1 << wl.bits, L),
+                       dim3(kSegThreadsS), segs_lds, s, ba);
+    hipLaunchKernelGGL((seg_sort_kernel<kSegThreads, kSegTiny>), dim3(1 << wl.bits, L),
+                       dim3(kSegThreads), seg_lds, s, ba);
     hipLaunchKernelGGL(big_pivot_kernel, dim3(wl.big_grid), dim3(kWave), 0, s, ba);
     hipLaunchKernelGGL(big_count_kernel, dim3(4 * wl.big_grid), dim3(256), 0, s, ba);
     hipLaunchKernelGGL(big_cscan_kernel, dim3(wl.big_grid), dim3(kWave), 0, s, ba);

@@ -120,6 +120,27 @@ def test_all_equal_large_and_segment_size_boundary():
     _check(keys)
 
 
+def test_segment_sizes_at_the_workgroup_boundaries():
+    """Segments (top 5 varying bits for n = 20000) of exactly 2048 and 2049
+    keys (the two LDS sort sizes) and 4096 / 4097 (the LDS sort and the big
+    path), with duplicates inside them; the rest spread over other digits."""
+    g = _rng(10)
+    n = 20000
+    keys = g.integers(0, 2**63, (2, n), dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    top = keys >> np.uint64(59)
+    for d in (3, 7, 11, 19):
+        keys[top == d] ^= np.uint64(1) << np.uint64(59)    # keep these digits empty
+    low = np.uint64((1 << 59) - 1)
+    start = 0
+    for d, size in ((3, 2048), (7, 2049), (11, 4096), (19, 4097)):
+        sl = slice(start, start + size)
+        keys[:, sl] = (keys[:, sl] & low) | (np.uint64(d) << np.uint64(59))
+        keys[:, start + 5:start + size:9] = keys[:, start:start + 1]   # a repeated key
+        start += size
+    keys[1] = keys[1, g.permutation(n)]
+    _check(keys, id_base=77)
+
+
 def test_skewed_short_keys_big_segments():
     """16-bit keys from a few values (clustered SRP codes): segments by the
     high byte are far larger than 8192 and differ only in the low byte."""
