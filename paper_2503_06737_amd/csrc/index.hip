@@ -39,6 +39,10 @@ constexpr int kWaves = kThreads / kWave;
 constexpr int kMsdBitsMax = 10;
 constexpr int kMsdRadixMax = 1 << kMsdBitsMax;
 constexpr int kRadix = 256;                // 8-bit digits below the segment digit
+// keys per thread of the segment scatter (a multiple of kItems: it may rank
+// several counted tiles at once; one measured fastest)
+constexpr int kMsdItems = kItems;
+constexpr int kMsdTile = kThreads * kMsdItems;
 constexpr int kSegThreads = 512;
 constexpr int kSegSmall = kSegThreads * kItems; // 4096: segments sorted by kSegThreads
 // segments of at most 2048 keys take a 256-thread workgroup with half the
@@ -151,6 +155,9 @@ __device__ __forceinline__ uint64_t wave_and64(uint64_t v)
 
 // f(i, keys[i]) for every i < cnt, split over the block with eight loads in
 // flight per thread (a single workgroup streams a whole part this way).
+// Loads past the end read the last key instead (and are ignored), so that
+// no load sits in a branch: the compiler then issues them together rather
+// than waiting for each.
 template <typename F>
 __device__ __forceinline__ void for_each_key(const uint64_t *keys, uint32_t cnt, F f)
 {
@@ -160,7 +167,7 @@ __device__ __forceinline__ void for_each_key(const uint64_t *keys, uint32_t cnt,
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const uint32_t i = base + u * nt + tid;
-            v[u] = i < cnt ? keys[i] : 0;
+            v[u] = keys[min(i, cnt - 1u)]; // clamped: no branch around the load
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -219,17 +226,21 @@ __global__ __launch_bounds__(kThreads) void mask_up_kernel(BuildArgs a)
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int64_t i = base + it * kThreads + threadIdx.x;
-        v[it] = full || i < a.n ? k[i] : 0;
+        v[it] = k[full ? i : min(i, a.n - 1)]; // clamped: no branch around the load
     }
     uint64_t vo = 0, va = ~0ull;
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int64_t i = base + it * kThreads + threadIdx.x;
-        if (full || i < a.n) {
-            vo |= v[it];
-            va &= v[it];
+        const uint64_t m = full || i < a.n ? ~0ull : 0ull;
+        vo |= v[it] & m;
+        va &= v[it] | ~m;
+    }
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t i = base + it * kThreads + threadIdx.x;
+        if (full || i < a.n)
             atomicAdd(&h[(uint32_t)(v[it] >> shift)], 1u);
-        }
     }
     vo = wave_or64(vo);
     va = wave_and64(va);
@@ -286,11 +297,15 @@ __global__ __launch_bounds__(kThreads) void msd_up_kernel(BuildArgs a)
     const int shift = top_shift(a.tor[t] & ~a.tand[t], a.msd_bits);
     const uint64_t *k = a.kin + (int64_t)t * a.key_ld;
     const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint64_t v[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it)
+        v[it] = k[min(base + it * kThreads + threadIdx.x, a.n - 1)];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int64_t i = base + it * kThreads + threadIdx.x;
         if (i < a.n)
-            atomicAdd(&h[(uint32_t)(k[i] >> shift) & (uint32_t)(R - 1)], 1u);
+            atomicAdd(&h[(uint32_t)(v[it] >> shift) & (uint32_t)(R - 1)], 1u);
     }
     __syncthreads();
     uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
@@ -429,27 +444,29 @@ __device__ __forceinline__ uint32_t count_below(uint32_t lo, uint32_t hi)
     return __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
 }
 
-template <int RMAX> struct ScatterLds {
-    // per-wave digit counts (a wave ranks at most 512 keys), then per-wave
-    // prefixes inside each digit (at most 8192)
+template <int RMAX, int IT = kItems> struct ScatterLds {
+    // per-wave digit counts (a wave ranks IT * 64 <= 1024 keys), then
+    // per-wave prefixes inside each digit (below the tile size)
     alignas(4) uint16_t whist[kWaves][RMAX];
     uint32_t lbase[RMAX];   // first sorted position of each digit in the tile
     uint32_t goff[RMAX];    // the caller's output offset of each digit
     uint32_t wsum[RMAX / kWave];
     uint32_t count[RMAX];   // the tile's count of each digit (for the caller)
-    uint16_t perm[kTile];   // tile position of the key at each sorted position
+    uint16_t perm[kThreads * IT]; // tile position of the key at each sorted position
+    static_assert(IT * kWave <= 1024 && kThreads * IT <= 65536, "16-bit counts");
 };
 
-// Stable scatter of one tile (1024 threads): keys (and ids, or id0 + i when
-// ids is NULL) [0, cnt) go to kout/iout at goff[digit] + (rank among the
-// tile's keys of that digit), digit = (key >> shift) & (2^bits - 1).  Wave w
-// ranks rows w*8 .. w*8+7 of 64 keys; the lanes holding the same digit come
+// Stable scatter of one tile of 1024 * IT keys (1024 threads): keys (and
+// ids, or id0 + i when ids is NULL) [0, cnt) go to kout/iout at
+// goff[digit] + (rank among the tile's keys of that digit), digit = (key >>
+// shift) & (2^bits - 1).  Wave w ranks rows w*IT .. w*IT+IT-1 of 64 keys;
+// the lanes holding the same digit come
 // from one ballot per digit bit.  Only the order is kept in LDS (the tile
 // position of each sorted position); the keys are read again (from cache)
 // in that order and written as contiguous digit runs, so two tiles fit in
 // a CU's LDS.  On return s.count[d] holds the tile's count of digit d.
-template <int RMAX, int RLOG = __builtin_ctz(RMAX)>
-__device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t *kin,
+template <int RMAX, int IT = kItems, int RLOG = __builtin_ctz(RMAX)>
+__device__ __forceinline__ void scatter_tile(ScatterLds<RMAX, IT> &s, const uint64_t *kin,
                                              const uint32_t *iin, uint32_t id0, int cnt,
                                              int shift, int bits, const uint32_t *goff,
                                              uint64_t *kout, uint32_t *iout)
@@ -463,26 +480,44 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
         s.goff[i] = goff[i];
     __syncthreads();
 
-    const int wbase = wid * (kWave * kItems);
-    uint32_t rank[kItems], dg[kItems];
+    const int wbase = wid * (kWave * IT);
+    // dg[it]: the digit, then the digit | rank << 16 (rank < IT * 64).
+    // Positions past the end rank after every real key of the last digit
+    // (they come last in the ranking order) and are never written.  When
+    // the digit lies in one 32-bit half of the key (always for the segment
+    // digit of 64-bit digests) only that half is read.
+    uint32_t dg[IT];
+    const uint32_t *kw = (const uint32_t *)kin;
+    if (shift >= 32 || shift + bits <= 32) {
+        const int h = shift >= 32 ? 1 : 0, sh = shift - 32 * h;
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        const int i = wbase + it * kWave + lane;
-        // positions past the end rank after every real key of the last
-        // digit (they come last in the ranking order); never written
-        dg[it] = i < cnt ? (uint32_t)(kin[i] >> shift) & dmask : dmask;
+        for (int it = 0; it < IT; ++it) {
+            const int i = wbase + it * kWave + lane;
+            // clamped load, and no select between it and a constant: the
+            // load then stays out of any branch and all are issued together
+            const uint32_t w = kw[2 * min(i, cnt - 1) + h];
+            dg[it] = ((w >> sh) & dmask) | (i < cnt ? 0u : dmask);
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int i = wbase + it * kWave + lane;
+            const uint64_t k = kin[min(i, cnt - 1)];
+            dg[it] = ((uint32_t)(k >> shift) & dmask) | (i < cnt ? 0u : dmask);
+        }
     }
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
         // digit bits at `bits` and above are zero: their ballots keep every lane
         uint32_t plo, phi;
         match_digit<RLOG>(dg[it], plo, phi);
         const uint32_t before = count_below(plo, phi);
         const uint32_t npeer = __popc(plo) + __popc(phi);
         // the first lane of each digit adds the row's count to its 16-bit
-        // counter (half of a 32-bit word; a wave counts at most 512 keys, so
-        // no carry crosses into the other half); every lane then reads the
-        // count including this row.  A wave's LDS operations run in order.
+        // counter (half of a 32-bit word; a wave counts at most 1024 keys,
+        // so no carry crosses into the other half); every lane then reads
+        // the count including this row.  A wave's LDS operations run in
+        // order.
         if (before == 0)
             __hip_atomic_fetch_add((uint32_t *)__builtin_assume_aligned(
                                        &s.whist[wid][dg[it] & ~1u], 4),
@@ -490,7 +525,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
                                    __HIP_MEMORY_SCOPE_WAVEFRONT);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        rank[it] = (uint32_t)s.whist[wid][dg[it]] + before - npeer;
+        dg[it] |= ((uint32_t)s.whist[wid][dg[it]] + before - npeer) << 16;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
@@ -507,7 +542,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
                 c[w] = s.whist[w0 + w][tid];
 #pragma unroll
             for (int w = 0; w < 8; ++w) {
-                s.whist[w0 + w][tid] = (uint16_t)tot; // prefix within the tile: < 8192
+                s.whist[w0 + w][tid] = (uint16_t)tot; // prefix within the tile
                 tot += c[w];
             }
         }
@@ -517,20 +552,37 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX> &s, const uint64_t
         s.lbase[tid] = excl;
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
         const int i = wbase + it * kWave + lane;
+        const uint32_t d = dg[it] & 0xffffu;
         if (i < cnt)
-            s.perm[s.lbase[dg[it]] + s.whist[wid][dg[it]] + rank[it]] = (uint16_t)i;
+            s.perm[s.lbase[d] + s.whist[wid][d] + (dg[it] >> 16)] = (uint16_t)i;
     }
     __syncthreads();
-    // the real keys hold sorted positions [0, cnt): padding ranks last
-    for (int q = tid; q < cnt; q += kThreads) {
-        const uint32_t i = s.perm[q];
-        const uint64_t k = kin[i];
-        const uint32_t d = (uint32_t)(k >> shift) & dmask;
-        const uint32_t g = s.goff[d] + ((uint32_t)q - s.lbase[d]);
-        kout[g] = k;
-        iout[g] = iin ? iin[i] : id0 + i;
+    // The real keys hold sorted positions [0, cnt): padding ranks last.
+    // All of a thread's positions at once (clamped reads, no branch before
+    // the stores), so that the reads of the keys overlap.
+    {
+        uint32_t pi[IT], iv[IT];
+        uint64_t kv[IT];
+#pragma unroll
+        for (int u = 0; u < IT; ++u)
+            pi[u] = s.perm[min(u * kThreads + tid, cnt - 1)];
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            kv[u] = kin[pi[u]];
+            iv[u] = iin ? iin[pi[u]] : id0 + pi[u];
+        }
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            const int q = u * kThreads + tid;
+            if (q < cnt) {
+                const uint32_t d = (uint32_t)(kv[u] >> shift) & dmask;
+                const uint32_t g = s.goff[d] + ((uint32_t)q - s.lbase[d]);
+                kout[g] = kv[u];
+                iout[g] = iv[u];
+            }
+        }
     }
     // tile digit counts for the caller (lbase is exclusive, so count = next - this)
     if (tid < R) {
@@ -546,16 +598,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
 msd_scatter_kernel(BuildArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    ScatterLds<kMsdRadixMax> &s = *(ScatterLds<kMsdRadixMax> *)lds;
+    ScatterLds<kMsdRadixMax, kMsdItems> &s = *(ScatterLds<kMsdRadixMax, kMsdItems> *)lds;
     const int t = blockIdx.y;
     const int R = 1 << a.msd_bits;
     const int shift = top_shift(a.tor[t] & ~a.tand[t], a.msd_bits);
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    const int cnt = (int)min((int64_t)kTile, a.n - base);
-    const uint32_t *goff = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
-    scatter_tile<kMsdRadixMax>(s, a.kin + (int64_t)t * a.key_ld + base, nullptr,
-                               a.id_base + (uint32_t)base, cnt, shift, a.msd_bits, goff,
-                               a.ka + (int64_t)t * a.n, a.ia + (int64_t)t * a.n);
+    // kMsdTile / kTile counted tiles at once: their run of a digit starts
+    // where the first tile's run starts and covers the others
+    const int64_t base = (int64_t)blockIdx.x * kMsdTile;
+    const int cnt = (int)min((int64_t)kMsdTile, a.n - base);
+    const uint32_t *goff =
+        a.tile_hist + ((int64_t)t * a.ntiles + (int64_t)blockIdx.x * (kMsdTile / kTile)) * R;
+    scatter_tile<kMsdRadixMax, kMsdItems>(s, a.kin + (int64_t)t * a.key_ld + base, nullptr,
+                                          a.id_base + (uint32_t)base, cnt, shift, a.msd_bits,
+                                          goff, a.ka + (int64_t)t * a.n, a.ia + (int64_t)t * a.n);
 }
 
 // ------------------------------------------------- segment sort in LDS
@@ -715,19 +770,20 @@ __device__ void seg_sort_body(SegLds<NT> &s, const uint64_t *kin, const uint32_t
 #pragma unroll
         for (int u = 0; u < kItems; ++u) {
             const int j = u * NT + tid;
-            kv[u] = j < cnt ? kin[j] : 0;
-            iv[u] = j < cnt ? iin[j] : 0;
+            kv[u] = kin[min(j, cnt - 1)]; // clamped: no branch around the loads
+            iv[u] = iin[min(j, cnt - 1)];
         }
+        // every slot j < NT * kItems is written (past cnt: never read), and
+        // the masks take only the real keys, without a branch
 #pragma unroll
         for (int u = 0; u < kItems; ++u) {
             const int j = u * NT + tid;
-            if (j < cnt) {
-                s.key[j] = kv[u];
-                s.id[j] = iv[u];
-                s.ix[0][j] = (uint16_t)j;
-                vo |= kv[u];
-                va &= kv[u];
-            }
+            const uint64_t m = j < cnt ? ~0ull : 0ull;
+            s.key[j] = kv[u];
+            s.id[j] = iv[u];
+            s.ix[0][j] = (uint16_t)j;
+            vo |= kv[u] & m;
+            va &= kv[u] | ~m;
         }
     }
     vo = wave_or64(vo);
@@ -788,10 +844,14 @@ __device__ void seg_sort_body(SegLds<NT> &s, const uint64_t *kin, const uint32_t
             }
         }
     }
-    for (int j = tid; j < cnt; j += NT) {
-        const uint16_t ix = s.ix[cur][j];
-        kout[j] = s.key[ix];
-        iout[j] = s.id[ix];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const int j = u * NT + tid;
+        if (j < cnt) {
+            const uint16_t ix = s.ix[cur][j];
+            kout[j] = s.key[ix];
+            iout[j] = s.id[ix];
+        }
     }
     __syncthreads();
 }
@@ -946,21 +1006,22 @@ __device__ __noinline__ void partition3(uint32_t (*cls)[4], const uint64_t *kin,
     for (uint32_t t0 = 0; t0 < cnt; t0 += kTile) {
         uint32_t cl[kItems], rank[kItems];
         uint32_t r0 = 0, r1 = 0, r2 = 0; // this wave's running class counts
+        // all loads first (clamped: no branch), then the classes
 #pragma unroll
         for (int it = 0; it < kItems; ++it) {
             const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
-            uint32_t c = 3;
-            if (i < cnt) {
-                const uint64_t k = kin[i];
-                c = k < pivot ? 0u : (k == pivot ? 1u : 2u);
-            }
+            const uint64_t k = kin[min(i, cnt - 1u)];
+            cl[it] = i >= cnt ? 3u : k < pivot ? 0u : (k == pivot ? 1u : 2u);
+        }
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t c = cl[it];
             const uint64_t b0 = __ballot(c == 0), b1 = __ballot(c == 1), b2 = __ballot(c == 2);
             const uint64_t mine = c == 0 ? b0 : (c == 1 ? b1 : b2);
             rank[it] = (c == 0 ? r0 : (c == 1 ? r1 : r2)) + __popcll(mine & lt);
             r0 += __popcll(b0);
             r1 += __popcll(b1);
             r2 += __popcll(b2);
-            cl[it] = c;
         }
         if (lane == 0) {
             cls[wid][0] = r0;
@@ -1282,9 +1343,20 @@ struct HeadArgs {
     int64_t *nuniq;     // [L]
 };
 
-__device__ __forceinline__ bool is_head(const uint64_t *k, int64_t i)
+// Loads for the head test of position i (clamped into [0, n) rather than
+// guarded, so that no load sits in a branch): x = key i, y = key i - 1.
+__device__ __forceinline__ void head_keys(const uint64_t *k, int64_t i, int64_t n, uint64_t &x,
+                                          uint64_t &y)
 {
-    return i == 0 || k[i] != k[i - 1];
+    const int64_t ic = min(i, n - 1);
+    x = k[ic];
+    y = k[ic > 0 ? ic - 1 : 0];
+}
+
+// Position i (< n) starts a run of equal keys.
+__device__ __forceinline__ bool is_head(int64_t i, int64_t n, uint64_t x, uint64_t y)
+{
+    return i < n && (i == 0 || x != y);
 }
 
 __global__ __launch_bounds__(kHeadThreads) void head_count_kernel(HeadArgs a)
@@ -1292,12 +1364,14 @@ __global__ __launch_bounds__(kHeadThreads) void head_count_kernel(HeadArgs a)
     const int t = blockIdx.y;
     const uint64_t *k = a.sk + (int64_t)t * a.n;
     int64_t base = (int64_t)blockIdx.x * kHeadTile;
+    uint64_t x[kHeadItems], y[kHeadItems];
+#pragma unroll
+    for (int it = 0; it < kHeadItems; ++it)
+        head_keys(k, base + it * kHeadThreads + threadIdx.x, a.n, x[it], y[it]);
     uint32_t c = 0;
-    for (int it = 0; it < kHeadItems; ++it) {
-        int64_t i = base + it * kHeadThreads + threadIdx.x;
-        if (i < a.n)
-            c += is_head(k, i);
-    }
+#pragma unroll
+    for (int it = 0; it < kHeadItems; ++it)
+        c += is_head(base + it * kHeadThreads + threadIdx.x, a.n, x[it], y[it]);
     c = wave_sum(c);
     __shared__ uint32_t s[kHeadThreads / kWave];
     if (lane_id() == 0)
@@ -1354,16 +1428,17 @@ __global__ __launch_bounds__(kHeadThreads) void head_write_kernel(HeadArgs a)
     // item it of thread tid is position base + it*256 + tid: tile order is (it, wave, lane)
     uint64_t bal[kHeadItems];
     uint64_t key[kHeadItems];
+    {
+        uint64_t prev[kHeadItems];
+#pragma unroll
+        for (int it = 0; it < kHeadItems; ++it)
+            head_keys(k, base + it * kHeadThreads + tid, a.n, key[it], prev[it]);
+#pragma unroll
+        for (int it = 0; it < kHeadItems; ++it)
+            bal[it] = __ballot(is_head(base + it * kHeadThreads + tid, a.n, key[it], prev[it]));
+    }
 #pragma unroll
     for (int it = 0; it < kHeadItems; ++it) {
-        int64_t i = base + it * kHeadThreads + tid;
-        bool h = false;
-        key[it] = 0;
-        if (i < a.n) {
-            key[it] = k[i];
-            h = i == 0 || key[it] != k[i - 1];
-        }
-        bal[it] = __ballot(h);
         if (lane == 0)
             pre[it][wid] = __popcll(bal[it]);
     }
@@ -1586,7 +1661,7 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     ba.bcount = (uint32_t *)(wb + wl.bcount);
     ba.stack = (uint32_t *)(wb + wl.stack);
 
-    const size_t scatter_lds = sizeof(ScatterLds<kMsdRadixMax>);
+    const size_t scatter_lds = sizeof(ScatterLds<kMsdRadixMax, kMsdItems>);
     const size_t seg_lds = sizeof(SegLds<kSegThreads>);
     const size_t segs_lds = sizeof(SegLds<kSegThreadsS>);
     const void *seg_fn = (const void *)seg_sort_kernel<kSegThreads, kSegTiny>;
@@ -1612,7 +1687,9 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     hipLaunchKernelGGL(msd_reset_kernel, dim3(L), dim3(kMsdRadixMax), 0, s, ba);
     hipLaunchKernelGGL(msd_up_kernel, tiles, dim3(kThreads), 0, s, ba);
     hipLaunchKernelGGL(msd_scan_kernel, dim3(L), dim3(kMsdRadixMax), 0, s, ba);
-    hipLaunchKernelGGL(msd_scatter_kernel, tiles, dim3(kThreads), scatter_lds, s, ba);
+    constexpr int tpm = kMsdTile / kTile;
+    hipLaunchKernelGGL(msd_scatter_kernel, dim3((wl.ntiles + tpm - 1) / tpm, L), dim3(kThreads),
+                       scatter_lds, s, ba);
     hipLaunchKernelGGL((seg_sort_kernel<kSegThreadsS, 0>), dim3(1 << wl.bits, L),
                        dim3(kSegThreadsS), segs_lds, s, ba);
     hipLaunchKernelGGL((seg_sort_kernel<kSegThreads, kSegTiny>), dim3(1 << wl.bits, L),
