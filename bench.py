@@ -187,7 +187,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded; image-like sparse rows, Bernoulli(0.2) x U(0,1))",
         "config": {"workload": wl.name, "n": n, "d": d, "K": K, "L": L, "m": m, "w": w,
-                   "family": "CS-E2LSH", "index": "64-bit LSD radix sort per table"},
+                   "family": "CS-E2LSH", "index": "per table: MSD split on the top varying bits, LDS sorts of the segments, parallel pivot split of heavy buckets"},
         "roofline": {"bound": "hbm", "achieved": round(hash_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4), "traffic": hash_traffic(),
                      "kernel": "hash_kernel (CS-E2LSH sketch + discretise + keys)",
