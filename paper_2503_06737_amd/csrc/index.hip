@@ -72,15 +72,19 @@ struct BuildArgs {
     uint32_t *seg_start;  // [L][2^B]
     uint64_t *ka, *kb;    // key buffers [L][n]; kb ends sorted
     uint32_t *ia, *ids;   // id buffers [L][n] (ids = the index's sorted_ids)
-    uint32_t *blist;      // [L * 2^B][8]: table, segment, first tile, tiles, pivot?, #<, #=
+    uint32_t *blist;      // [L * 2^B][8]: table, segment, first tile, tiles, pivot?, #<, #=,
+                          // parts handed to the LDS sorts (bit 0: <, bit 1: >)
     uint64_t *bpivot;     // [L * 2^B]: pivot key of a big segment
     uint32_t *btile;      // [maxbt][2]: big segment, tile within it
     uint32_t *tcls;       // [maxbt][4]: per tile: class counts, then class offsets
-    uint32_t *bcount;     // [3]: big segments, stack overflows (0 unless a bound fails), tiles
+    uint32_t *bcount;     // [kCounts]: big segments, stack overflows (0 unless a bound fails),
+                          // big tiles, parts of 1..2048 keys, parts of 2049..4096 keys
+    uint32_t *plist;      // [2][2 * L * 2^B][3]: those parts (table, start, size)
     uint32_t *stack;      // [grid][kStackMax][3]: start, size, buffer
 };
 
-constexpr int kBig = 8; // words per big-segment entry
+constexpr int kBig = 8;    // words per big-segment entry
+constexpr int kCounts = 8; // words of BuildArgs::bcount
 
 __device__ __forceinline__ int top_shift(uint64_t vm, int bits)
 {
@@ -130,9 +134,10 @@ __global__ __launch_bounds__(256) void build_init_kernel(BuildArgs a)
             a.tor[i] = 0;
             a.tand[i] = ~0ull;
         }
-        if (i < 3)
-            a.bcount[i] = 0;
     }
+    // the counters do not depend on nseg (which can be as small as 2)
+    if (blockIdx.x == 0 && threadIdx.x < kCounts)
+        a.bcount[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------------------ mask
@@ -347,6 +352,7 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
         b[2] = t0;
         b[3] = ntl;
         b[4] = 0;
+        b[7] = 0;
         for (uint32_t k = 0; k < ntl; ++k) {
             a.btile[2 * (t0 + k)] = b0;
             a.btile[2 * (t0 + k) + 1] = k;
@@ -759,8 +765,9 @@ __device__ __forceinline__ void seg_rank_pass(SegLds<NT> &s, const uint16_t *src
 // ascend on entry, every pass is stable -- and writes them to kout / iout
 // (which may alias kin / iin: everything is read before anything is written).
 template <int NT>
-__device__ void seg_sort_body(SegLds<NT> &s, const uint64_t *kin, const uint32_t *iin, int cnt,
-                              uint64_t *kout, uint32_t *iout)
+__device__ __forceinline__ void seg_sort_body(SegLds<NT> &s, const uint64_t *kin,
+                                              const uint32_t *iin, int cnt, uint64_t *kout,
+                                              uint32_t *iout)
 {
     const int tid = threadIdx.x;
     uint64_t vo = 0, va = ~0ull;
@@ -967,29 +974,86 @@ __global__ __launch_bounds__(256) void big_count_kernel(BuildArgs a)
 __global__ __launch_bounds__(kWave) void big_cscan_kernel(BuildArgs a)
 {
     const uint32_t nb = a.bcount[0];
-    for (uint32_t bi = blockIdx.x * kWave + threadIdx.x; bi < nb; bi += gridDim.x * kWave) {
-        uint32_t *b = a.blist + kBig * bi;
-        if (!b[4])
-            continue;
-        const int e = ((int)b[0] << a.msd_bits) + (int)b[1];
-        uint32_t nlt = 0, neq = 0;
-        for (uint32_t k = 0; k < b[3]; ++k) {
-            nlt += a.tcls[4 * (b[2] + k)];
-            neq += a.tcls[4 * (b[2] + k) + 1];
+    const uint64_t lt = lanemask_lt();
+    // every lane of the wave runs the same number of rounds (the ballots
+    // below need the whole wave); lanes past nb do nothing
+    const uint32_t rounds = (nb + gridDim.x * kWave - 1) / (gridDim.x * kWave);
+    for (uint32_t r = 0; r < rounds; ++r) {
+        const uint32_t bi = (r * gridDim.x + blockIdx.x) * kWave + threadIdx.x;
+        uint32_t *b = a.blist + kBig * min(bi, nb - 1u);
+        const bool piv = bi < nb && b[4];
+        uint32_t pst[2] = {0, 0}, pn[2] = {0, 0};
+        if (piv) {
+            const int e = ((int)b[0] << a.msd_bits) + (int)b[1];
+            uint32_t nlt = 0, neq = 0;
+            for (uint32_t k = 0; k < b[3]; ++k) {
+                nlt += a.tcls[4 * (b[2] + k)];
+                neq += a.tcls[4 * (b[2] + k) + 1];
+            }
+            uint32_t o0 = a.seg_start[e], o1 = o0 + nlt, o2 = o1 + neq;
+            for (uint32_t k = 0; k < b[3]; ++k) {
+                uint32_t *c = a.tcls + 4 * (b[2] + k);
+                const uint32_t c0 = c[0], c1 = c[1], c2 = c[2];
+                c[0] = o0;
+                c[1] = o1;
+                c[2] = o2;
+                o0 += c0;
+                o1 += c1;
+                o2 += c2;
+            }
+            b[5] = nlt;
+            b[6] = neq;
+            const uint32_t size = a.ghist[e], st = a.seg_start[e];
+            pst[0] = st;
+            pn[0] = nlt;
+            pst[1] = st + nlt + neq;
+            pn[1] = size - nlt - neq;
         }
-        uint32_t o0 = a.seg_start[e], o1 = o0 + nlt, o2 = o1 + neq;
-        for (uint32_t k = 0; k < b[3]; ++k) {
-            uint32_t *c = a.tcls + 4 * (b[2] + k);
-            const uint32_t c0 = c[0], c1 = c[1], c2 = c[2];
-            c[0] = o0;
-            c[1] = o1;
-            c[2] = o2;
-            o0 += c0;
-            o1 += c1;
-            o2 += c2;
+        // The < and > parts of at most 4096 keys go to the segment sorts
+        // (several workgroups per CU) rather than to the big-segment sort.
+        // One atomic add per wave and list reserves the wave's slots.
+        uint32_t handed = 0;
+        for (int q = 0; q < 2; ++q) {
+            for (int cls = 0; cls < 2; ++cls) {
+                const bool take = pn[q] > 0u && pn[q] <= (uint32_t)kSegSmall &&
+                                  (pn[q] <= (uint32_t)kSegTiny ? 0 : 1) == cls;
+                const uint64_t bal = __ballot(take);
+                if (!bal)
+                    continue;
+                uint32_t first = 0;
+                if (lane_id() == __builtin_ctzll(bal))
+                    first = atomicAdd(&a.bcount[3 + cls], (uint32_t)__popcll(bal));
+                first = __shfl(first, __builtin_ctzll(bal), kWave);
+                if (take) {
+                    const uint32_t slot = first + (uint32_t)__popcll(bal & lt);
+                    uint32_t *p =
+                        a.plist + 3 * ((size_t)cls * 2 * ((size_t)a.L << a.msd_bits) + slot);
+                    p[0] = b[0];
+                    p[1] = pst[q];
+                    p[2] = pn[q];
+                    handed |= 1u << q;
+                }
+            }
         }
-        b[5] = nlt;
-        b[6] = neq;
+        if (piv)
+            b[7] = handed;
+    }
+}
+
+// The < and > parts listed by big_cscan (after big_part has written them to
+// kb / ids), sorted in place: class CLS 0 (1..2048 keys, 256 threads) or 1
+// (2049..4096, 512 threads); workgroup g takes entries g, g + grid, ...
+template <int NT, int CLS>
+__global__ __launch_bounds__(NT) void part_sort_kernel(BuildArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    SegLds<NT> &s = *(SegLds<NT> *)lds;
+    const uint32_t count = a.bcount[3 + CLS];
+    const uint32_t *list = a.plist + 3 * (size_t)CLS * 2 * ((size_t)a.L << a.msd_bits);
+    for (uint32_t j = blockIdx.x; j < count; j += gridDim.x) {
+        const uint32_t *p = list + 3 * (size_t)j;
+        const int64_t off = (int64_t)p[0] * a.n + p[1];
+        seg_sort_body<NT>(s, a.kb + off, a.ids + off, (int)p[2], a.kb + off, a.ids + off);
     }
 }
 
@@ -1148,13 +1212,13 @@ __global__ __launch_bounds__(kThreads) void big_sort_kernel(BuildArgs a)
             const uint32_t st = a.seg_start[e], size = a.ghist[e];
             if (b[4]) {
                 const uint32_t nlt = b[5], neq = b[6];
-                if (nlt) {
+                if (nlt && !(b[7] & 1u)) {
                     stk[3 * tp] = st;
                     stk[3 * tp + 1] = nlt;
                     stk[3 * tp + 2] = 1;
                     ++tp;
                 }
-                if (size - nlt - neq) {
+                if (size - nlt - neq && !(b[7] & 2u)) {
                     stk[3 * tp] = st + nlt + neq;
                     stk[3 * tp + 1] = size - nlt - neq;
                     stk[3 * tp + 2] = 1;
@@ -1511,7 +1575,7 @@ IndexLayout index_layout(int64_t n, int32_t L)
 
 struct WsLayout {
     size_t ka, kb, ia, tor, tand, tile_hist, ghist, seg_start, blist, bpivot, btile, tcls, bcount,
-        stack, tile_cnt, total;
+        plist, stack, tile_cnt, total;
     int ntiles, nhtiles, bits, big_grid, maxbt;
 };
 
@@ -1558,7 +1622,8 @@ WsLayout ws_layout(int64_t n, int32_t L)
     w.bpivot = take(nseg * 8);
     w.btile = take((size_t)w.maxbt * 8);
     w.tcls = take((size_t)w.maxbt * 16);
-    w.bcount = take(16);
+    w.bcount = take(kCounts * 4);
+    w.plist = take(2 * 2 * nseg * 3 * 4);
     w.stack = take((size_t)w.big_grid * kStackMax * 12);
     w.tile_cnt = take((size_t)L * (w.nhtiles > 0 ? w.nhtiles : 1) * 4);
     w.total = o;
@@ -1659,6 +1724,7 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     ba.btile = (uint32_t *)(wb + wl.btile);
     ba.tcls = (uint32_t *)(wb + wl.tcls);
     ba.bcount = (uint32_t *)(wb + wl.bcount);
+    ba.plist = (uint32_t *)(wb + wl.plist);
     ba.stack = (uint32_t *)(wb + wl.stack);
 
     const size_t scatter_lds = sizeof(ScatterLds<kMsdRadixMax, kMsdItems>);
@@ -1666,6 +1732,8 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     const size_t segs_lds = sizeof(SegLds<kSegThreadsS>);
     const void *seg_fn = (const void *)seg_sort_kernel<kSegThreads, kSegTiny>;
     const void *segs_fn = (const void *)seg_sort_kernel<kSegThreadsS, 0>;
+    const void *part_fn = (const void *)part_sort_kernel<kSegThreads, 1>;
+    const void *parts_fn = (const void *)part_sort_kernel<kSegThreadsS, 0>;
     const size_t big_lds = sizeof(BigLds);
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)msd_scatter_kernel,
@@ -1674,6 +1742,10 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
         (e = hipFuncSetAttribute(seg_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)seg_lds)) != hipSuccess ||
         (e = hipFuncSetAttribute(segs_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)segs_lds)) != hipSuccess ||
+        (e = hipFuncSetAttribute(part_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)seg_lds)) != hipSuccess ||
+        (e = hipFuncSetAttribute(parts_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)segs_lds)) != hipSuccess ||
         (e = hipFuncSetAttribute((const void *)big_sort_kernel,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)big_lds)) !=
@@ -1698,6 +1770,12 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     hipLaunchKernelGGL(big_count_kernel, dim3(4 * wl.big_grid), dim3(256), 0, s, ba);
     hipLaunchKernelGGL(big_cscan_kernel, dim3(wl.big_grid), dim3(kWave), 0, s, ba);
     hipLaunchKernelGGL(big_part_kernel, dim3(2 * wl.big_grid), dim3(kThreads), 0, s, ba);
+    // the small parts of the split segments: as many workgroups as fit on
+    // the 256 CUs at once (four and two per CU), at most two per big segment
+    hipLaunchKernelGGL((part_sort_kernel<kSegThreadsS, 0>), dim3(min(2 * nseg, 4 * 256)),
+                       dim3(kSegThreadsS), segs_lds, s, ba);
+    hipLaunchKernelGGL((part_sort_kernel<kSegThreads, 1>), dim3(min(2 * nseg, 2 * 256)),
+                       dim3(kSegThreads), seg_lds, s, ba);
     hipLaunchKernelGGL(big_sort_kernel, dim3(wl.big_grid), dim3(kThreads), big_lds, s, ba);
 
     HeadArgs ha;

@@ -64,6 +64,17 @@ def test_all_equal_and_single_and_extremes():
     _check(k)
 
 
+def test_single_table_two_segments():
+    """One table of at most 2048 keys has only two segments: the build's
+    counters must still start at zero (they are cleared apart from the
+    per-segment arrays)."""
+    g = _rng(11)
+    for n in (1, 5, 1000, 2048):
+        keys = g.integers(0, 2**63, (1, n), dtype=np.int64).astype(np.uint64)
+        keys[0, ::3] = keys[0, 0]
+        _check(keys)
+
+
 def test_empty_index():
     dev()
     import torch
