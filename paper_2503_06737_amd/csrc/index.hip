@@ -1407,36 +1407,60 @@ struct HeadArgs {
     int64_t *nuniq;     // [L]
 };
 
-// Loads for the head test of position i (clamped into [0, n) rather than
-// guarded, so that no load sits in a branch): x = key i, y = key i - 1.
-__device__ __forceinline__ void head_keys(const uint64_t *k, int64_t i, int64_t n, uint64_t &x,
-                                          uint64_t &y)
+// A 64-bit value from the lane below (wave_shr:1 on each half); lane 0
+// receives `fill`.
+__device__ __forceinline__ uint64_t lane_below(uint64_t x, uint64_t fill)
 {
-    const int64_t ic = min(i, n - 1);
-    x = k[ic];
-    y = k[ic > 0 ? ic - 1 : 0];
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(
+        (int)(uint32_t)fill, (int)(uint32_t)x, 0x138, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+        (int)(uint32_t)(fill >> 32), (int)(uint32_t)(x >> 32), 0x138, 0xf, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// Position i (< n) starts a run of equal keys.
-__device__ __forceinline__ bool is_head(int64_t i, int64_t n, uint64_t x, uint64_t y)
+__device__ __forceinline__ uint64_t lane63(uint64_t x)
 {
-    return i < n && (i == 0 || x != y);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, kWave - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), kWave - 1);
+    return ((uint64_t)hi << 32) | lo;
 }
 
+// A wave's chunk of kHeadItems rows of 64 keys, positions wb + it*64 + lane
+// (loads clamped into [0, n) rather than guarded, so that none sits in a
+// branch).  hb[it]: ballot of the positions (< n) that start a run.  The
+// key before a position is the lane below's, for lane 0 the last lane of
+// the row before, for the chunk's first row the key before the chunk: one
+// load per key.
+__device__ __forceinline__ void chunk_heads(const uint64_t *k, int64_t wb, int64_t n,
+                                            uint64_t (&x)[kHeadItems], uint64_t (&hb)[kHeadItems])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int it = 0; it < kHeadItems; ++it)
+        x[it] = k[min(wb + it * kWave + lane, n - 1)];
+    uint64_t before = k[max(min(wb - 1, n - 1), (int64_t)0)];
+#pragma unroll
+    for (int it = 0; it < kHeadItems; ++it) {
+        const uint64_t prev = lane_below(x[it], before);
+        const int64_t i = wb + it * kWave + lane;
+        hb[it] = __ballot(i < n && (i == 0 || x[it] != prev));
+        before = lane63(x[it]);
+    }
+}
+
+// Tile of kHeadTile keys: wave w takes positions [w * 64 * kHeadItems, ...).
 __global__ __launch_bounds__(kHeadThreads) void head_count_kernel(HeadArgs a)
 {
     const int t = blockIdx.y;
     const uint64_t *k = a.sk + (int64_t)t * a.n;
-    int64_t base = (int64_t)blockIdx.x * kHeadTile;
-    uint64_t x[kHeadItems], y[kHeadItems];
-#pragma unroll
-    for (int it = 0; it < kHeadItems; ++it)
-        head_keys(k, base + it * kHeadThreads + threadIdx.x, a.n, x[it], y[it]);
+    const int64_t wb =
+        (int64_t)blockIdx.x * kHeadTile + (threadIdx.x / kWave) * (kWave * kHeadItems);
+    uint64_t x[kHeadItems], hb[kHeadItems];
+    chunk_heads(k, wb, a.n, x, hb);
     uint32_t c = 0;
 #pragma unroll
     for (int it = 0; it < kHeadItems; ++it)
-        c += is_head(base + it * kHeadThreads + threadIdx.x, a.n, x[it], y[it]);
-    c = wave_sum(c);
+        c += (uint32_t)__popcll(hb[it]);
     __shared__ uint32_t s[kHeadThreads / kWave];
     if (lane_id() == 0)
         s[threadIdx.x / kWave] = c;
@@ -1484,49 +1508,35 @@ __global__ __launch_bounds__(1024) void head_scan_kernel(HeadArgs a)
 __global__ __launch_bounds__(kHeadThreads) void head_write_kernel(HeadArgs a)
 {
     constexpr int kW = kHeadThreads / kWave;
-    __shared__ uint32_t pre[kHeadItems][kW];
+    __shared__ uint32_t wtot[kW];
     const int t = blockIdx.y;
     const uint64_t *k = a.sk + (int64_t)t * a.n;
-    const int64_t base = (int64_t)blockIdx.x * kHeadTile;
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-    // item it of thread tid is position base + it*256 + tid: tile order is (it, wave, lane)
-    uint64_t bal[kHeadItems];
-    uint64_t key[kHeadItems];
-    {
-        uint64_t prev[kHeadItems];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int64_t wb = (int64_t)blockIdx.x * kHeadTile + wid * (kWave * kHeadItems);
+    uint64_t x[kHeadItems], hb[kHeadItems];
+    chunk_heads(k, wb, a.n, x, hb);
+    uint32_t tot = 0;
 #pragma unroll
-        for (int it = 0; it < kHeadItems; ++it)
-            head_keys(k, base + it * kHeadThreads + tid, a.n, key[it], prev[it]);
-#pragma unroll
-        for (int it = 0; it < kHeadItems; ++it)
-            bal[it] = __ballot(is_head(base + it * kHeadThreads + tid, a.n, key[it], prev[it]));
-    }
-#pragma unroll
-    for (int it = 0; it < kHeadItems; ++it) {
-        if (lane == 0)
-            pre[it][wid] = __popcll(bal[it]);
-    }
+    for (int it = 0; it < kHeadItems; ++it)
+        tot += (uint32_t)__popcll(hb[it]);
+    if (lane == 0)
+        wtot[wid] = tot;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = a.tile_cnt[(int64_t)t * a.ntiles + blockIdx.x];
-        for (int it = 0; it < kHeadItems; ++it)
-            for (int w = 0; w < kW; ++w) {
-                uint32_t c = pre[it][w];
-                pre[it][w] = run;
-                run += c;
-            }
-    }
-    __syncthreads();
+    // heads before this wave's chunk: the tile's start, then the waves before
+    uint32_t run = a.tile_cnt[(int64_t)t * a.ntiles + blockIdx.x];
+    for (int w = 0; w < wid; ++w)
+        run += wtot[w];
     uint64_t *uk = a.ukeys + (int64_t)t * a.n;
     uint32_t *of = a.offs + (int64_t)t * (a.n + 1);
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int it = 0; it < kHeadItems; ++it) {
-        if ((bal[it] >> lane) & 1ull) {
-            uint32_t u = pre[it][wid] + __popcll(bal[it] & lt);
-            uk[u] = key[it];
-            of[u] = (uint32_t)(base + it * kHeadThreads + tid);
+        if ((hb[it] >> lane) & 1ull) {
+            const uint32_t u = run + (uint32_t)__popcll(hb[it] & lt);
+            uk[u] = x[it];
+            of[u] = (uint32_t)(wb + it * kWave + lane);
         }
+        run += (uint32_t)__popcll(hb[it]);
     }
 }
 
