@@ -1589,13 +1589,14 @@ struct WsLayout {
     int ntiles, nhtiles, bits, big_grid, maxbt;
 };
 
-// Segment digit width: about 1024 keys per segment (a workgroup per
-// segment has a fixed cost, so segments are not made smaller than that), at
-// most 2^10 segments.
+// Segment digit width: about 2048 keys per segment, at most 2^10 segments.
+// A segment sort has a fixed cost per workgroup, so at n = 1M keys per table
+// 2^9 segments built faster than 2^10 (fewer, longer digit runs in the
+// scatter too) and than 2^8 (more heavy segments for the big path).
 int msd_bits_for(int64_t n)
 {
     int b = 1;
-    while (b < lsh::kMsdBitsMax && ((int64_t)1024 << b) < n)
+    while (b < lsh::kMsdBitsMax && ((int64_t)2048 << b) < n)
         ++b;
     return b;
 }

@@ -132,11 +132,11 @@ def test_all_equal_large_and_segment_size_boundary():
 
 
 def test_segment_sizes_at_the_workgroup_boundaries():
-    """Segments (top 5 varying bits for n = 20000) of exactly 2048 and 2049
+    """Segments (top 5 varying bits for n = 40000) of exactly 2048 and 2049
     keys (the two LDS sort sizes) and 4096 / 4097 (the LDS sort and the big
     path), with duplicates inside them; the rest spread over other digits."""
     g = _rng(10)
-    n = 20000
+    n = 40000
     keys = g.integers(0, 2**63, (2, n), dtype=np.int64).astype(np.uint64) * np.uint64(2)
     top = keys >> np.uint64(59)
     for d in (3, 7, 11, 19):
