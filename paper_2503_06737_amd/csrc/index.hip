@@ -99,25 +99,33 @@ __device__ __forceinline__ bool chunk_varies(uint64_t vm, int p)
     return ((vm >> (8 * p)) & 255u) != 0;
 }
 
-// Exclusive scan of v over threads [0, R) of the block (R <= blockDim.x);
-// every thread calls it.  wsum: LDS scratch of R / 64 words.
+// Inclusive sum over the lanes of a wave: shifts within rows of 16 lanes,
+// then the last lane of a row broadcast to the rows above it.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true); // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true); // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true); // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true); // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false); // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); // row_bcast:31
+    return x;
+}
+
+// Exclusive scan of v over threads [0, R) of the block (R <= blockDim.x,
+// at most 64 waves); every thread calls it.  wsum: LDS scratch of R / 64
+// words.  Within a wave by DPP; across waves every wave sums the totals of
+// the waves before it the same way.
 __device__ __forceinline__ uint32_t scan_excl(uint32_t v, int R, uint32_t *wsum)
 {
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const uint32_t v0 = tid < R ? v : 0u;
-    uint32_t x = v0;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, kWave);
-        if (lane >= o)
-            x += y;
-    }
+    const uint32_t x = wave_incl_scan(v0);
     if (tid < R && (lane == kWave - 1 || tid == R - 1))
         wsum[w] = x;
     __syncthreads();
-    uint32_t pre = 0;
-    for (int q = 0; q < w && q * kWave < R; ++q)
-        pre += wsum[q];
+    const uint32_t y = lane < w && lane * kWave < R ? wsum[lane] : 0u;
+    const uint32_t pre = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(y), kWave - 1);
     __syncthreads();
     return pre + x - v0;
 }
@@ -142,20 +150,33 @@ __global__ __launch_bounds__(256) void build_init_kernel(BuildArgs a)
 
 // ------------------------------------------------------------------ mask
 
+// OR / AND of a 32-bit value over the wave, the same DPP steps as
+// wave_incl_scan (lanes without a source contribute the identity); the
+// last lane's result is the wave's, read back as a uniform value.
+template <bool OR>
+__device__ __forceinline__ uint32_t wave_bits32(uint32_t x)
+{
+    const int id = OR ? 0 : -1;
+    auto f = [](uint32_t u, int y) { return OR ? u | (uint32_t)y : u & (uint32_t)y; };
+    x = f(x, __builtin_amdgcn_update_dpp(id, (int)x, 0x111, 0xf, 0xf, false)); // row_shr:1
+    x = f(x, __builtin_amdgcn_update_dpp(id, (int)x, 0x112, 0xf, 0xf, false)); // row_shr:2
+    x = f(x, __builtin_amdgcn_update_dpp(id, (int)x, 0x114, 0xf, 0xf, false)); // row_shr:4
+    x = f(x, __builtin_amdgcn_update_dpp(id, (int)x, 0x118, 0xf, 0xf, false)); // row_shr:8
+    x = f(x, __builtin_amdgcn_update_dpp(id, (int)x, 0x142, 0xa, 0xf, false)); // row_bcast:15
+    x = f(x, __builtin_amdgcn_update_dpp(id, (int)x, 0x143, 0xc, 0xf, false)); // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
+}
+
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v |= __shfl_xor(v, o, kWave);
-    return v;
+    return ((uint64_t)wave_bits32<true>((uint32_t)(v >> 32)) << 32) |
+           wave_bits32<true>((uint32_t)v);
 }
 
 __device__ __forceinline__ uint64_t wave_and64(uint64_t v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v &= __shfl_xor(v, o, kWave);
-    return v;
+    return ((uint64_t)wave_bits32<false>((uint32_t)(v >> 32)) << 32) |
+           wave_bits32<false>((uint32_t)v);
 }
 
 // f(i, keys[i]) for every i < cnt, split over the block with eight loads in
@@ -634,19 +655,6 @@ template <int NT> struct SegLds {
     uint64_t so[NW], sa[NW];
     int flag;
 };
-
-// Inclusive sum over the lanes of a wave: shifts within rows of 16 lanes,
-// then the last lane of a row broadcast to the rows above it.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
-{
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true); // row_shr:1
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true); // row_shr:2
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true); // row_shr:4
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true); // row_shr:8
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false); // row_bcast:15
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); // row_bcast:31
-    return x;
-}
 
 // One stable counting pass of the index array src -> dst by chunk p of the
 // keys, with digit counts in s.whist[buf] (zero on entry; s.whist[buf ^ 1]
