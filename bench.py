@@ -3,8 +3,9 @@
 Workload (image-like rows): n = 1,000,000 points, d = 784, FP32 with ~80%
 exact zeros (x = Bernoulli(0.2) * U(0,1)), K = 16 components per table,
 L = 64 tables (m = 1024), w = 4.  One step = CS-E2LSH hashing of every point
-(bucket keys only) + the index build (per-table radix sort of the 64-bit keys
-and bucket offsets), from points resident in HBM to finished tables.
+(bucket keys only) + the index build (per table, the (key, id) pairs put in
+key order and the bucket offsets), from points resident in HBM to finished
+tables.
 
 Printed as one JSON line.  Beside the headline value the same run measures
 the dense E2LSH baseline (Y = X R on FP32 matrix cores, same index build),

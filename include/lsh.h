@@ -169,8 +169,12 @@ size_t lsh_index_bytes(int64_t n, int32_t L);
 /* Bytes of temporary workspace lsh_build_index needs. */
 size_t lsh_build_workspace_bytes(int64_t n, int32_t L);
 
-/* Group the n points into buckets, per table: a stable 64-bit LSD radix sort
- * of (key, id) with ids = id_base + i, then distinct keys and bucket offsets.
+/* Group the n points into buckets, per table (Section 3.1: every point is
+ * stored in the bucket of its key in every table): the (key, id) pairs, ids =
+ * id_base + i, are put in (key, id) order, then the distinct keys and bucket
+ * offsets are written.  The order is built by a split on the top varying key
+ * bits, sorts of the resulting segments in LDS and a pivot split of heavy
+ * buckets; the result equals a stable sort of the keys.
  * keys: [L][key_ld] (key_ld 0 means n).  mem: index storage (lsh_index_bytes,
  * 256-byte aligned), ws: workspace (lsh_build_workspace_bytes, 256-byte
  * aligned; free for reuse once the enqueued work completes).  On success

@@ -1,4 +1,4 @@
-"""GPU index build (per-table stable radix sort + bucket offsets) against the
+"""GPU index build (per-table (key, id) order + bucket offsets) against the
 oracle's grouping: bit-exact sorted ids, distinct keys, offsets, counts."""
 import numpy as np
 import pytest
