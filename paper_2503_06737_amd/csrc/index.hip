@@ -1076,14 +1076,20 @@ __device__ __noinline__ void partition3(uint32_t (*cls)[4], const uint64_t *kin,
     const int tid = threadIdx.x, wid = tid / kWave, lane = lane_id();
     const uint64_t lt = lanemask_lt();
     for (uint32_t t0 = 0; t0 < cnt; t0 += kTile) {
-        uint32_t cl[kItems], rank[kItems];
+        uint32_t cl[kItems], rank[kItems], iv[kItems];
+        uint64_t kv[kItems];
         uint32_t r0 = 0, r1 = 0, r2 = 0; // this wave's running class counts
         // all loads first (clamped: no branch), then the classes
 #pragma unroll
         for (int it = 0; it < kItems; ++it) {
             const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
-            const uint64_t k = kin[min(i, cnt - 1u)];
-            cl[it] = i >= cnt ? 3u : k < pivot ? 0u : (k == pivot ? 1u : 2u);
+            kv[it] = kin[min(i, cnt - 1u)];
+            iv[it] = iin[min(i, cnt - 1u)];
+        }
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
+            cl[it] = i >= cnt ? 3u : kv[it] < pivot ? 0u : (kv[it] == pivot ? 1u : 2u);
         }
 #pragma unroll
         for (int it = 0; it < kItems; ++it) {
@@ -1112,10 +1118,9 @@ __device__ __noinline__ void partition3(uint32_t (*cls)[4], const uint64_t *kin,
         for (int it = 0; it < kItems; ++it) {
             const uint32_t c = cl[it];
             if (c < 3) {
-                const uint32_t i = t0 + wid * (kWave * kItems) + it * kWave + lane;
                 const uint32_t pos = (c == 0 ? q0 : (c == 1 ? q1 : q2)) + rank[it];
-                kout[pos] = kin[i];
-                iout[pos] = iin[i];
+                kout[pos] = kv[it];
+                iout[pos] = iv[it];
             }
         }
         __syncthreads();
