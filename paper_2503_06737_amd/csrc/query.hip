@@ -74,6 +74,52 @@ __device__ __forceinline__ float load_val(const void *x, int dt, const float *sc
     return sc * __uint_as_float(__float_as_uint(mag) | ((b & 0x80u) << 24));
 }
 
+// Element off of a row of type DT (sc: the row's scale; 1 for FP32).
+template <int DT>
+__device__ __forceinline__ float load_dt(const void *x, float sc, int64_t off)
+{
+    if constexpr (DT == LSH_F32)
+        return ((const float *)x)[off];
+    if constexpr (DT == LSH_BF16)
+        return sc * __uint_as_float((uint32_t)((const uint16_t *)x)[off] << 16);
+    const uint32_t b = ((const uint8_t *)x)[off];
+    const float mag = __uint_as_float((b & 0x7fu) << 20) * 0x1.0p120f;
+    return sc * __uint_as_float(__float_as_uint(mag) | ((b & 0x80u) << 24));
+}
+
+// Sums over one candidate row by a wave (each lane a partial sum): squared
+// differences to the query (E2LSH) or the dot product and the row's squared
+// norm (SRP).  Four loads per lane are in flight at a time: their indexes
+// are clamped into [0, d) rather than guarded, and the lanes past d add 0.
+template <int DT>
+__device__ __forceinline__ void score_row(const QueryArgs &a, const float *qv, int64_t row,
+                                          float &acc, float &xx)
+{
+    const int lane = lane_id();
+    const float sc = DT != LSH_F32 && a.bscale ? a.bscale[row] : 1.0f;
+    const int64_t rb = row * a.bld;
+    for (int j0 = 0; j0 < a.d; j0 += 4 * kWave) {
+        float xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            xv[u] = load_dt<DT>(a.bx, sc, rb + min(j0 + u * kWave + lane, a.d - 1));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = j0 + u * kWave + lane;
+            const bool in = j < a.d;
+            const float x = in ? xv[u] : 0.0f;
+            const float qj = in ? qv[j] : 0.0f;
+            if (a.metric == LSH_E2LSH) {
+                const float df = qj - x;
+                acc = fmaf(df, df, acc);
+            } else {
+                acc = fmaf(qj, x, acc);
+                xx = fmaf(x, x, xx);
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *a, uint32_t lo, uint32_t hi,
                                                      uint32_t v)
 {
@@ -326,16 +372,12 @@ __global__ __launch_bounds__(kQThreads) void query_kernel(QueryArgs a)
         for (uint32_t c = wid; c < uc; c += kQWaves) {
             const int64_t row = cand[c];
             float acc = 0.0f, xx = 0.0f;
-            for (int j = lane; j < a.d; j += kWave) {
-                float xv = load_val(a.bx, a.bdt, a.bscale, row, a.bld, j);
-                if (a.metric == LSH_E2LSH) {
-                    float df = qv[j] - xv;
-                    acc = fmaf(df, df, acc);
-                } else {
-                    acc = fmaf(qv[j], xv, acc);
-                    xx = fmaf(xv, xv, xx);
-                }
-            }
+            if (a.bdt == LSH_F32)
+                score_row<LSH_F32>(a, qv, row, acc, xx);
+            else if (a.bdt == LSH_BF16)
+                score_row<LSH_BF16>(a, qv, row, acc, xx);
+            else
+                score_row<LSH_FP8_E4M3FN>(a, qv, row, acc, xx);
             acc = wave_sum(acc);
             xx = wave_sum(xx);
             float sc;
