@@ -89,8 +89,11 @@ __device__ __forceinline__ float load_dt(const void *x, float sc, int64_t off)
 
 // Sums over one candidate row by a wave (each lane a partial sum): squared
 // differences to the query (E2LSH) or the dot product and the row's squared
-// norm (SRP).  Four loads per lane are in flight at a time: their indexes
-// are clamped into [0, d) rather than guarded, and the lanes past d add 0.
+// norm (SRP).  kScoreLoads loads per lane are in flight at a time (a row of
+// up to 1024 elements in one round trip): their indexes are clamped into
+// [0, d) rather than guarded, and the lanes past d add 0.
+constexpr int kScoreLoads = 16;
+
 template <int DT>
 __device__ __forceinline__ void score_row(const QueryArgs &a, const float *qv, int64_t row,
                                           float &acc, float &xx)
@@ -98,13 +101,13 @@ __device__ __forceinline__ void score_row(const QueryArgs &a, const float *qv, i
     const int lane = lane_id();
     const float sc = DT != LSH_F32 && a.bscale ? a.bscale[row] : 1.0f;
     const int64_t rb = row * a.bld;
-    for (int j0 = 0; j0 < a.d; j0 += 4 * kWave) {
-        float xv[4];
+    for (int j0 = 0; j0 < a.d; j0 += kScoreLoads * kWave) {
+        float xv[kScoreLoads];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kScoreLoads; ++u)
             xv[u] = load_dt<DT>(a.bx, sc, rb + min(j0 + u * kWave + lane, a.d - 1));
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kScoreLoads; ++u) {
             const int j = j0 + u * kWave + lane;
             const bool in = j < a.d;
             const float x = in ? xv[u] : 0.0f;
@@ -131,6 +134,45 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *a, uint32_t 
             hi = mid;
     }
     return lo;
+}
+
+// First index of uk[0, n) (ascending) whose key is >= key.  Probes are
+// placed by interpolation on the key values (the bucket keys of 64-bit
+// digests are spread evenly over the key range); after a probe that leaves
+// more than half of the range, the next one bisects, so a search takes at
+// most about twice the probes of plain bisection.
+__device__ __forceinline__ int64_t lower_bound_keys(const uint64_t *uk, int64_t n, uint64_t key)
+{
+    if (n == 0)
+        return 0;
+    uint64_t klo = uk[0], khi = uk[n - 1];
+    if (key <= klo)
+        return 0;
+    if (key > khi)
+        return n;
+    int64_t lo = 0, hi = n - 1; // uk[lo] < key <= uk[hi]: the answer is in (lo, hi]
+    bool bisect = false;
+    while (hi - lo > 1) {
+        const int64_t len = hi - lo;
+        int64_t mid;
+        if (bisect) {
+            mid = lo + (len >> 1);
+        } else {
+            const double f = (double)(key - klo) / (double)(khi - klo);
+            mid = lo + (int64_t)(f * (double)len);
+            mid = max(lo + 1, min(hi - 1, mid));
+        }
+        const uint64_t km = uk[mid];
+        if (km < key) {
+            lo = mid;
+            klo = km;
+        } else {
+            hi = mid;
+            khi = km;
+        }
+        bisect = !bisect && 2 * (hi - lo) > len;
+    }
+    return hi;
 }
 
 // Bitonic sort of n (power of two) 64-bit keys in LDS, ascending, whole block.
@@ -238,21 +280,17 @@ __global__ __launch_bounds__(kQThreads) void query_kernel(QueryArgs a)
         const QSeg &S = a.seg[sg];
         uint64_t key = a.qkeys[(int64_t)t * a.qkey_ld + q];
         const uint64_t *uk = S.ukeys + (int64_t)t * S.n;
-        int64_t lo = 0, hi = S.nuniq[t];
-        while (lo < hi) {
-            int64_t mid = lo + ((hi - lo) >> 1);
-            if (uk[mid] < key)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
+        const int64_t nu = S.nuniq[t];
+        const int64_t lo = lower_bound_keys(uk, nu, key);
         uint32_t st = 0, en = 0;
-        if (lo < S.nuniq[t] && uk[lo] == key) {
+        if (lo < nu && uk[lo] == key) {
             const uint32_t *of = S.offs + (int64_t)t * (S.n + 1);
             st = of[lo];
             en = of[lo + 1];
             // ids of a bucket ascend: drop the tail at or above the watermark
-            en = lower_bound_u32(S.ids + (int64_t)t * S.n, st, en, a.watermark);
+            const uint32_t *ids = S.ids + (int64_t)t * S.n;
+            if (ids[en - 1] >= a.watermark)
+                en = lower_bound_u32(ids, st, en, a.watermark);
         }
         lst_start[li] = st;
         lst_cur[li] = st;
