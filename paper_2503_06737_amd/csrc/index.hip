@@ -233,7 +233,7 @@ __device__ __forceinline__ void block_or_and(const uint64_t *keys, int64_t cnt, 
 
 // OR / AND of every key of a table and, guessing that the table's top key
 // bit varies (true of 64-bit digests), the tile's counts of the segment
-// digit key >> (64 - B).  msd_reset / msd_up recount the tables where the
+// digit key >> (64 - B).  msd_up recounts the tables where the
 // guess fails (short SRP keys).
 __global__ __launch_bounds__(kThreads) void mask_up_kernel(BuildArgs a)
 {
@@ -285,11 +285,8 @@ __global__ __launch_bounds__(kThreads) void mask_up_kernel(BuildArgs a)
         atomicAnd((unsigned long long *)&a.tand[t], (unsigned long long)sa[0]);
     }
     uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
-    for (int i = threadIdx.x; i < R; i += kThreads) {
+    for (int i = threadIdx.x; i < R; i += kThreads)
         th[i] = h[i];
-        if (h[i])
-            atomicAdd(&a.ghist[(t << a.msd_bits) + i], h[i]);
-    }
 }
 
 // ------------------------------------------------------------ segment digit
@@ -297,15 +294,6 @@ __global__ __launch_bounds__(kThreads) void mask_up_kernel(BuildArgs a)
 __device__ __forceinline__ bool guess_holds(const BuildArgs &a, int t)
 {
     return top_shift(a.tor[t] & ~a.tand[t], a.msd_bits) == 64 - a.msd_bits;
-}
-
-// Tables whose top key bit does not vary: clear the guessed segment sizes.
-__global__ __launch_bounds__(kMsdRadixMax) void msd_reset_kernel(BuildArgs a)
-{
-    const int t = blockIdx.x;
-    if (guess_holds(a, t) || (int)threadIdx.x >= (1 << a.msd_bits))
-        return;
-    a.ghist[(t << a.msd_bits) + threadIdx.x] = 0;
 }
 
 // Tables whose top key bit does not vary: count the segment digit (the top
@@ -335,13 +323,11 @@ __global__ __launch_bounds__(kThreads) void msd_up_kernel(BuildArgs a)
     }
     __syncthreads();
     uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
-    for (int i = threadIdx.x; i < R; i += blockDim.x) {
+    for (int i = threadIdx.x; i < R; i += blockDim.x)
         th[i] = h[i];
-        if (h[i])
-            atomicAdd(&a.ghist[(t << a.msd_bits) + i], h[i]);
-    }
 }
 
+// ghist[t][d] <- size of segment d (the sum of the tile counts);
 // tile_hist[t][tile][d] <- global start of the tile's run of digit d;
 // seg_start[t][d] <- start of segment d.  Segments larger than an LDS sort
 // join the big list (blist, btile) in a range the table reserves with one
@@ -354,7 +340,23 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
     __shared__ uint32_t wsum[kMsdRadixMax / kWave];
     __shared__ uint32_t bres[2];
     const int d = threadIdx.x;
-    const uint32_t c = d < R ? a.ghist[(t << a.msd_bits) + d] : 0u;
+    uint32_t *th = a.tile_hist + (int64_t)t * a.ntiles * R + d;
+    uint32_t c = 0;
+    if (d < R) {
+        int tile = 0;
+        for (; tile + 8 <= a.ntiles; tile += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = th[(int64_t)(tile + u) * R];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                c += v[u];
+        }
+        for (; tile < a.ntiles; ++tile)
+            c += th[(int64_t)tile * R];
+        a.ghist[(t << a.msd_bits) + d] = c;
+    }
     uint32_t run = scan_excl(c, R, wsum);
     const bool big = d < R && c > (uint32_t)kSegSmall;
     const uint32_t ntl = big ? (c + kTile - 1) / kTile : 0u;
@@ -382,7 +384,6 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
     if (d >= R)
         return;
     a.seg_start[(t << a.msd_bits) + d] = run;
-    uint32_t *th = a.tile_hist + (int64_t)t * a.ntiles * R + d;
     int tile = 0;
     for (; tile + 8 <= a.ntiles; tile += 8) {
         uint32_t v[8];
@@ -1780,7 +1781,6 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     dim3 tiles(wl.ntiles, L);
     hipLaunchKernelGGL(build_init_kernel, dim3((nseg + 255) / 256), dim3(256), 0, s, ba);
     hipLaunchKernelGGL(mask_up_kernel, tiles, dim3(kThreads), 0, s, ba);
-    hipLaunchKernelGGL(msd_reset_kernel, dim3(L), dim3(kMsdRadixMax), 0, s, ba);
     hipLaunchKernelGGL(msd_up_kernel, tiles, dim3(kThreads), 0, s, ba);
     hipLaunchKernelGGL(msd_scan_kernel, dim3(L), dim3(kMsdRadixMax), 0, s, ba);
     constexpr int tpm = kMsdTile / kTile;
