@@ -19,10 +19,12 @@
 //                an adjacent pair shows two distinct keys that agree on them);
 //   4. big     - larger segments (heavy buckets, skewed digits): a sampled
 //                pivot key splits each in parallel over tiles into less /
-//                equal / greater parts; then one 1024-thread workgroup per
-//                segment splits the rest recursively (pivot or top varying
-//                byte): parts holding a single key are copied, parts of at
-//                most 8192 keys are sorted in LDS;
+//                equal / greater parts; less and greater parts of at most
+//                4096 keys are sorted like the segments of step 3; one
+//                1024-thread workgroup per segment splits the rest
+//                recursively (pivot or top varying byte): parts holding a
+//                single key are copied, parts of at most 8192 keys are sorted
+//                in LDS;
 //   5. heads   - run heads are counted per tile, scanned per table, and the
 //                distinct keys and bucket start offsets are written.
 // Every scatter ranks keys stably (one ballot per digit bit gives the lanes
