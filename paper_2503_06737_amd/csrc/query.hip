@@ -87,37 +87,50 @@ __device__ __forceinline__ float load_dt(const void *x, float sc, int64_t off)
     return sc * __uint_as_float(__float_as_uint(mag) | ((b & 0x80u) << 24));
 }
 
-// Sums over one candidate row by a wave (each lane a partial sum): squared
-// differences to the query (E2LSH) or the dot product and the row's squared
-// norm (SRP).  kScoreLoads loads per lane are in flight at a time (a row of
-// up to 1024 elements in one round trip): their indexes are clamped into
-// [0, d) rather than guarded, and the lanes past d add 0.
+// Sums over NR candidate rows by a wave (each lane a partial sum per row):
+// squared differences to the query (E2LSH) or the dot product and the row's
+// squared norm (SRP).  kScoreLoads loads per lane and row are in flight at a
+// time (rows of up to 1024 elements in one round trip): their indexes are
+// clamped into [0, d) rather than guarded, and the lanes past d add 0.
 constexpr int kScoreLoads = 16;
 
-template <int DT>
-__device__ __forceinline__ void score_row(const QueryArgs &a, const float *qv, int64_t row,
-                                          float &acc, float &xx)
+template <int DT, int NR>
+__device__ __forceinline__ void score_rows(const QueryArgs &a, const float *qv,
+                                           const int64_t (&row)[NR], float (&acc)[NR],
+                                           float (&xx)[NR])
 {
     const int lane = lane_id();
-    const float sc = DT != LSH_F32 && a.bscale ? a.bscale[row] : 1.0f;
-    const int64_t rb = row * a.bld;
-    for (int j0 = 0; j0 < a.d; j0 += kScoreLoads * kWave) {
-        float xv[kScoreLoads];
+    float sc[NR];
+    int64_t rb[NR];
 #pragma unroll
-        for (int u = 0; u < kScoreLoads; ++u)
-            xv[u] = load_dt<DT>(a.bx, sc, rb + min(j0 + u * kWave + lane, a.d - 1));
+    for (int r = 0; r < NR; ++r) {
+        sc[r] = DT != LSH_F32 && a.bscale ? a.bscale[row[r]] : 1.0f;
+        rb[r] = row[r] * a.bld;
+        acc[r] = 0.0f;
+        xx[r] = 0.0f;
+    }
+    for (int j0 = 0; j0 < a.d; j0 += kScoreLoads * kWave) {
+        float xv[NR][kScoreLoads];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int u = 0; u < kScoreLoads; ++u)
+                xv[r][u] = load_dt<DT>(a.bx, sc[r], rb[r] + min(j0 + u * kWave + lane, a.d - 1));
 #pragma unroll
         for (int u = 0; u < kScoreLoads; ++u) {
             const int j = j0 + u * kWave + lane;
             const bool in = j < a.d;
-            const float x = in ? xv[u] : 0.0f;
             const float qj = in ? qv[j] : 0.0f;
-            if (a.metric == LSH_E2LSH) {
-                const float df = qj - x;
-                acc = fmaf(df, df, acc);
-            } else {
-                acc = fmaf(qj, x, acc);
-                xx = fmaf(x, x, xx);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const float x = in ? xv[r][u] : 0.0f;
+                if (a.metric == LSH_E2LSH) {
+                    const float df = qj - x;
+                    acc[r] = fmaf(df, df, acc[r]);
+                } else {
+                    acc[r] = fmaf(qj, x, acc[r]);
+                    xx[r] = fmaf(x, x, xx[r]);
+                }
             }
         }
     }
@@ -406,28 +419,33 @@ __global__ __launch_bounds__(kQThreads) void query_kernel(QueryArgs a)
         }
         __syncthreads();
         const uint32_t uc = s_ucount;
-        // score: one wave per candidate row
-        for (uint32_t c = wid; c < uc; c += kQWaves) {
-            const int64_t row = cand[c];
-            float acc = 0.0f, xx = 0.0f;
+        // score: a wave takes candidates c and c + kQWaves together (their
+        // loads overlap); the second one repeats the first past the end
+        for (uint32_t c = wid; c < uc; c += 2 * kQWaves) {
+            const bool two = c + kQWaves < uc;
+            const int64_t row[2] = {cand[c], cand[two ? c + kQWaves : c]};
+            float acc[2], xx[2];
             if (a.bdt == LSH_F32)
-                score_row<LSH_F32>(a, qv, row, acc, xx);
+                score_rows<LSH_F32, 2>(a, qv, row, acc, xx);
             else if (a.bdt == LSH_BF16)
-                score_row<LSH_BF16>(a, qv, row, acc, xx);
+                score_rows<LSH_BF16, 2>(a, qv, row, acc, xx);
             else
-                score_row<LSH_FP8_E4M3FN>(a, qv, row, acc, xx);
-            acc = wave_sum(acc);
-            xx = wave_sum(xx);
-            float sc;
-            if (a.metric == LSH_E2LSH) {
-                sc = sqrtf(acc);
-            } else {
-                float xn = sqrtf(xx);
-                float cs = (qn > 0.0f && xn > 0.0f) ? acc / (qn * xn) : 0.0f;
-                sc = 1.0f - cs;
+                score_rows<LSH_FP8_E4M3FN, 2>(a, qv, row, acc, xx);
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const float ac = wave_sum(acc[r]), xs = wave_sum(xx[r]);
+                float sc;
+                if (a.metric == LSH_E2LSH) {
+                    sc = sqrtf(ac);
+                } else {
+                    const float xn = sqrtf(xs);
+                    const float cs = (qn > 0.0f && xn > 0.0f) ? ac / (qn * xn) : 0.0f;
+                    sc = 1.0f - cs;
+                }
+                if (lane == 0 && (r == 0 || two))
+                    sbuf[c + r * kQWaves] =
+                        ((uint64_t)__float_as_uint(fmaxf(sc, 0.0f)) << 32) | (uint64_t)row[r];
             }
-            if (lane == 0)
-                sbuf[c] = ((uint64_t)__float_as_uint(fmaxf(sc, 0.0f)) << 32) | (uint64_t)row;
         }
         __syncthreads();
         // merge with the running top-k
