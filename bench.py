@@ -10,9 +10,11 @@ tables.
 Printed as one JSON line.  Beside the headline value the same run measures
 the dense E2LSH baseline (Y = X R on FP32 matrix cores, same index build),
 CS-SRP and dense SRP, query latency (p50/p99 of hash + probe + re-rank of
-query batches against the built index), per-kernel timings with HIP events
-on the stream the kernels run on, and the FP64 CPU oracle on a bounded
-sample of the same workload.
+query batches against the built index), the serving loop under sustained and
+overloaded request streams, CS against HCS at 500k x 4096, BF16/FP8 hashing
+with and without the FP64 recheck, per-kernel timings with HIP events on the
+stream the kernels run on, and the FP64 CPU oracle on the same workload (all
+rows hashed and one index built on the host cores).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
