@@ -184,15 +184,11 @@ template <> struct Elem<LSH_FP8_E4M3FN> {
     static constexpr int per16 = 16;
 };
 
-// OCP E4M3FN -> FP32.  The 7 magnitude bits shifted to bits 20..26 form an
-// FP32 number whose exponent is the FP8 exponent re-biased by 120 (normal
-// values) or an FP32 subnormal holding mantissa * 2^-129 (FP8 subnormals);
-// scaling by 2^120 restores both exactly.  (The NaN pattern is not
-// special-cased: quantised data never holds it.)
-__device__ __forceinline__ float fp8_to_f32(uint32_t byte)
+// OCP E4M3FN -> FP32 by the gfx950 conversion instruction (exact: every
+// E4M3FN value, subnormals included, is an FP32 number).  byte 0 of w.
+__device__ __forceinline__ float fp8_to_f32(uint32_t w)
 {
-    float mag = __uint_as_float((byte & 0x7fu) << 20) * 0x1.0p120f;
-    return __uint_as_float(__float_as_uint(mag) | ((byte & 0x80u) << 24));
+    return __builtin_amdgcn_cvt_f32_fp8((int)w, 0);
 }
 
 // Element e of a 16-byte chunk (ALIGNED) or the single element of a chunk.
@@ -212,8 +208,8 @@ template <int DT, bool AL> __device__ __forceinline__ float chunk_value(u32x4 v,
             return __uint_as_float(word);
         else if constexpr (DT == LSH_BF16)
             return __uint_as_float((e & 1) ? (word & 0xffff0000u) : (word << 16));
-        else
-            return fp8_to_f32((word >> (8 * (e & 3))) & 0xffu);
+        else // bytes 0-1 or 2-3 of the word as a pair: one conversion per two values
+            return __builtin_amdgcn_cvt_pk_f32_fp8((int)word, (e & 2) != 0)[e & 1];
     }
 }
 
