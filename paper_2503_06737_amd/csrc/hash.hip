@@ -209,7 +209,8 @@ template <int DT, bool AL> __device__ __forceinline__ float chunk_value(u32x4 v,
         else if constexpr (DT == LSH_BF16)
             return __uint_as_float((e & 1) ? (word & 0xffff0000u) : (word << 16));
         else // bytes 0-1 or 2-3 of the word as a pair: one conversion per two values
-            return __builtin_amdgcn_cvt_pk_f32_fp8((int)word, (e & 2) != 0)[e & 1];
+            return (e & 2) ? __builtin_amdgcn_cvt_pk_f32_fp8((int)word, true)[e & 1]
+                           : __builtin_amdgcn_cvt_pk_f32_fp8((int)word, false)[e & 1];
     }
 }
 
