@@ -25,8 +25,10 @@
 //                recursively (pivot or top varying byte): parts holding a
 //                single key are copied, parts of at most 8192 keys are sorted
 //                in LDS;
-//   5. heads   - run heads are counted per tile, scanned per table, and the
-//                distinct keys and bucket start offsets are written.
+//   5. heads   - one pass over the sorted keys: each tile counts its run
+//                heads, takes the count before it from its predecessors (a
+//                decoupled look-back) and writes the distinct keys and
+//                bucket start offsets.
 // Every scatter ranks keys stably (one ballot per digit bit gives the lanes
 // of a wave that share a digit), so ids stay ascending inside a bucket.
 
@@ -56,7 +58,7 @@ constexpr int kChunks = 8;     // 8-bit chunks of a key (a segment's varying bit
 constexpr int kFastChunks = 3; // chunks sorted before the adjacent-pair check
 constexpr int kStackMax = 16 * kRadix; // pending parts of one big segment
 
-constexpr int kHeadThreads = 256;
+constexpr int kHeadThreads = 1024;
 constexpr int kHeadItems = 16;
 constexpr int kHeadTile = kHeadThreads * kHeadItems;
 
@@ -1416,12 +1418,28 @@ struct HeadArgs {
     const uint64_t *sk; // sorted keys [L][n]
     int64_t n;
     int32_t L;
-    int32_t ntiles;
-    uint32_t *tile_cnt; // [L][ntiles] -> exclusive base
+    int32_t ntiles;     // head tiles per table
+    uint64_t *status;   // [L][ntiles] tile status words (zero on entry)
+    uint32_t *counter;  // [L][16] tile ids handed out per table (element 0 of a
+                        // 64-byte line each; zero on entry)
+    uint32_t *errors;   // waits that gave up (zero on entry; stays zero)
     uint64_t *ukeys;    // [L][n]
     uint32_t *offs;     // [L][n+1]
     int64_t *nuniq;     // [L]
 };
+
+// Tile status word: flag in bits 62..63 (0: not yet published, kHeadAgg: the
+// tile's own head count, kHeadPre: the heads up to and including the tile),
+// count in bits 0..31.
+constexpr uint64_t kHeadAgg = 1ull << 62, kHeadPre = 2ull << 62;
+constexpr int kSpinMax = 1 << 16; // polls of one status word (about 0.1 s)
+
+__global__ __launch_bounds__(256) void fill_u64_kernel(uint64_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
 
 // A 64-bit value from the lane below (wave_shr:1 on each half); lane 0
 // receives `fill`.
@@ -1464,71 +1482,29 @@ __device__ __forceinline__ void chunk_heads(const uint64_t *k, int64_t wb, int64
     }
 }
 
-// Tile of kHeadTile keys: wave w takes positions [w * 64 * kHeadItems, ...).
-__global__ __launch_bounds__(kHeadThreads) void head_count_kernel(HeadArgs a)
-{
-    const int t = blockIdx.y;
-    const uint64_t *k = a.sk + (int64_t)t * a.n;
-    const int64_t wb =
-        (int64_t)blockIdx.x * kHeadTile + (threadIdx.x / kWave) * (kWave * kHeadItems);
-    uint64_t x[kHeadItems], hb[kHeadItems];
-    chunk_heads(k, wb, a.n, x, hb);
-    uint32_t c = 0;
-#pragma unroll
-    for (int it = 0; it < kHeadItems; ++it)
-        c += (uint32_t)__popcll(hb[it]);
-    __shared__ uint32_t s[kHeadThreads / kWave];
-    if (lane_id() == 0)
-        s[threadIdx.x / kWave] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (int w = 0; w < kHeadThreads / kWave; ++w)
-            tot += s[w];
-        a.tile_cnt[(int64_t)t * a.ntiles + blockIdx.x] = tot;
-    }
-}
-
-__global__ __launch_bounds__(1024) void head_scan_kernel(HeadArgs a)
-{
-    const int t = blockIdx.x;
-    uint32_t *c = a.tile_cnt + (int64_t)t * a.ntiles;
-    __shared__ uint32_t part[1024];
-    const int tid = threadIdx.x;
-    // each thread scans a contiguous run of tiles
-    int per = (a.ntiles + 1023) / 1024;
-    int lo = tid * per, hi = lo + per < a.ntiles ? lo + per : a.ntiles;
-    uint32_t s = 0;
-    for (int i = lo; i < hi; ++i)
-        s += c[i];
-    part[tid] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[tid] - s;
-    for (int i = lo; i < hi; ++i) {
-        uint32_t v = c[i];
-        c[i] = run;
-        run += v;
-    }
-    if (tid == 1023) {
-        a.nuniq[t] = part[1023];
-        a.offs[(int64_t)t * (a.n + 1) + part[1023]] = (uint32_t)a.n;
-    }
-}
-
-__global__ __launch_bounds__(kHeadThreads) void head_write_kernel(HeadArgs a)
+// Run heads of every table in one pass (a decoupled look-back).  The
+// workgroups of table t (blockIdx.y) take their tile ids from the table's
+// counter in the order they start, so every tile a tile waits for has
+// already started and runs to its end.  A tile counts its
+// heads and publishes the count, then adds its predecessors' counts back to
+// the first one that has published its inclusive count, publishes its own
+// inclusive count and writes its distinct keys and bucket starts.  The
+// status words are device-scope atomics (coherent across the XCDs' caches).
+// A wait gives up after kSpinMax polls of a window and counts an error, so
+// every wave exits whatever happens (by the ordering argument the count
+// stays zero).
+__global__ __launch_bounds__(kHeadThreads) void head_kernel(HeadArgs a)
 {
     constexpr int kW = kHeadThreads / kWave;
-    __shared__ uint32_t wtot[kW];
-    const int t = blockIdx.y;
-    const uint64_t *k = a.sk + (int64_t)t * a.n;
+    __shared__ uint32_t wtot[kW], s_g, s_excl;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
-    const int64_t wb = (int64_t)blockIdx.x * kHeadTile + wid * (kWave * kHeadItems);
+    const int t = blockIdx.y;
+    if (threadIdx.x == 0)
+        s_g = atomicAdd(&a.counter[16 * t], 1u);
+    __syncthreads();
+    const int tile = (int)s_g;
+    const uint64_t *k = a.sk + (int64_t)t * a.n;
+    const int64_t wb = (int64_t)tile * kHeadTile + wid * (kWave * kHeadItems);
     uint64_t x[kHeadItems], hb[kHeadItems];
     chunk_heads(k, wb, a.n, x, hb);
     uint32_t tot = 0;
@@ -1538,8 +1514,55 @@ __global__ __launch_bounds__(kHeadThreads) void head_write_kernel(HeadArgs a)
     if (lane == 0)
         wtot[wid] = tot;
     __syncthreads();
-    // heads before this wave's chunk: the tile's start, then the waves before
-    uint32_t run = a.tile_cnt[(int64_t)t * a.ntiles + blockIdx.x];
+    // wave 0 publishes the tile's count and looks back over windows of 64
+    // predecessors (lane i reads tile - 1 - i; positions before tile 0 count
+    // as an inclusive count of 0): it adds the counts of the lanes up to the
+    // first one holding an inclusive count, once all of them are published
+    if (wid == 0) {
+        uint32_t agg = 0;
+        for (int w = 0; w < kW; ++w)
+            agg += wtot[w];
+        uint64_t *st = a.status + (int64_t)t * a.ntiles;
+        if (lane == 0 && tile > 0)
+            __hip_atomic_store(&st[tile], kHeadAgg | agg, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t excl = 0;
+        int spin = 0;
+        for (int top = tile - 1; top >= 0;) {
+            const int j = top - lane;
+            const uint64_t v = j >= 0 ? __hip_atomic_load(&st[j], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : kHeadPre;
+            const uint64_t pre = __ballot((v >> 62) == 2), nil = __ballot((v >> 62) == 0);
+            const int fp = pre ? __builtin_ctzll(pre) : kWave; // first inclusive count
+            const uint64_t need = fp == kWave ? ~0ull : (2ull << fp) - 1ull;
+            if (nil & need) {
+                if (++spin == kSpinMax) {
+                    if (lane == 0)
+                        atomicAdd(a.errors, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += wave_sum(lane <= fp ? (uint32_t)v : 0u);
+            if (fp < kWave)
+                break;
+            top -= kWave;
+        }
+        if (lane == 0) {
+            __hip_atomic_store(&st[tile], kHeadPre | (excl + agg), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            s_excl = excl;
+            if (tile == a.ntiles - 1) {
+                a.nuniq[t] = excl + agg;
+                a.offs[(int64_t)t * (a.n + 1) + excl + agg] = (uint32_t)a.n;
+            }
+        }
+    }
+    __syncthreads();
+    // heads before this wave's chunk: the tiles before, then the waves before
+    uint32_t run = s_excl;
     for (int w = 0; w < wid; ++w)
         run += wtot[w];
     uint64_t *uk = a.ukeys + (int64_t)t * a.n;
@@ -1601,7 +1624,7 @@ IndexLayout index_layout(int64_t n, int32_t L)
 
 struct WsLayout {
     size_t ka, kb, ia, tor, tand, tile_hist, ghist, seg_start, blist, bpivot, btile, tcls, bcount,
-        plist, stack, tile_cnt, total;
+        plist, stack, hstat, total;
     int ntiles, nhtiles, bits, big_grid, maxbt;
 };
 
@@ -1652,7 +1675,7 @@ WsLayout ws_layout(int64_t n, int32_t L)
     w.bcount = take(kCounts * 4);
     w.plist = take(2 * 2 * nseg * 3 * 4);
     w.stack = take((size_t)w.big_grid * kStackMax * 12);
-    w.tile_cnt = take((size_t)L * (w.nhtiles > 0 ? w.nhtiles : 1) * 4);
+    w.hstat = take(((size_t)L * (w.nhtiles > 0 ? w.nhtiles : 1) + 8 * (size_t)L + 1) * 8);
     w.total = o;
     return w;
 }
@@ -1809,14 +1832,16 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     ha.n = n;
     ha.L = L;
     ha.ntiles = wl.nhtiles;
-    ha.tile_cnt = (uint32_t *)(wb + wl.tile_cnt);
+    ha.status = (uint64_t *)(wb + wl.hstat);
+    ha.counter = (uint32_t *)(ha.status + (size_t)L * wl.nhtiles);
+    ha.errors = ha.counter + 16 * (size_t)L;
     ha.ukeys = idx->ukeys;
     ha.offs = idx->offs;
     ha.nuniq = idx->nuniq;
-    dim3 htiles(wl.nhtiles, L);
-    hipLaunchKernelGGL(head_count_kernel, htiles, dim3(kHeadThreads), 0, s, ha);
-    hipLaunchKernelGGL(head_scan_kernel, dim3(L), dim3(1024), 0, s, ha);
-    hipLaunchKernelGGL(head_write_kernel, htiles, dim3(kHeadThreads), 0, s, ha);
+    const int64_t nstat = (int64_t)L * wl.nhtiles + 8 * (int64_t)L + 1;
+    const unsigned fill_grid = (unsigned)(nstat / 256 < 1024 ? nstat / 256 + 1 : 1024);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(fill_grid), dim3(256), 0, s, ha.status, nstat);
+    hipLaunchKernelGGL(head_kernel, dim3(wl.nhtiles, L), dim3(kHeadThreads), 0, s, ha);
     e = hipGetLastError();
     if (e != hipSuccess)
         return fail("index kernels", e);
