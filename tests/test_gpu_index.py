@@ -75,6 +75,15 @@ def test_single_table_two_segments():
         _check(keys)
 
 
+def test_head_look_back_over_many_tiles():
+    """More than 64 head tiles (16K keys each) in one table: a tile's look-back
+    crosses several windows of predecessors; many duplicates, ragged end."""
+    g = _rng(12)
+    n = 70 * 16384 + 123
+    keys = g.integers(0, 200000, (1, n)).astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+    _check(keys, id_base=5)
+
+
 def test_empty_index():
     dev()
     import torch
