@@ -453,15 +453,15 @@ __device__ __forceinline__ void match_4bits(uint32_t dg, uint32_t &lo, uint32_t 
 template <int NB>
 __device__ __forceinline__ void match_digit(uint32_t dg, uint32_t &lo, uint32_t &hi)
 {
-    static_assert(NB == 8 || NB == 10, "digit widths used here");
+    static_assert(NB >= 8 && NB <= 10, "digit widths used here");
     lo = ~0u;
     hi = ~0u;
     match_4bits<0>(dg, lo, hi);
     match_4bits<4>(dg, lo, hi);
-    if constexpr (NB == 10) {
-        // the last two bits in C: the compiler fuses them the same way
+    if constexpr (NB > 8) {
+        // the bits past 8 in C: the compiler fuses them the same way
 #pragma unroll
-        for (int b = 8; b < 10; ++b) {
+        for (int b = 8; b < NB; ++b) {
             const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)dg, b, 1);
             const uint64_t bal = __ballot(m != 0u);
             lo &= ~((uint32_t)bal ^ m);
@@ -640,9 +640,20 @@ msd_scatter_kernel(BuildArgs a)
     const int cnt = (int)min((int64_t)kMsdTile, a.n - base);
     const uint32_t *goff =
         a.tile_hist + ((int64_t)t * a.ntiles + (int64_t)blockIdx.x * (kMsdTile / kTile)) * R;
-    scatter_tile<kMsdRadixMax, kMsdItems>(s, a.kin + (int64_t)t * a.key_ld + base, nullptr,
-                                          a.id_base + (uint32_t)base, cnt, shift, a.msd_bits,
-                                          goff, a.ka + (int64_t)t * a.n, a.ia + (int64_t)t * a.n);
+    // one ballot per digit bit that can be set (B at most 8, 9 or 10)
+    const uint64_t *kin = a.kin + (int64_t)t * a.key_ld + base;
+    uint64_t *ko = a.ka + (int64_t)t * a.n;
+    uint32_t *io = a.ia + (int64_t)t * a.n;
+    const uint32_t id0 = a.id_base + (uint32_t)base;
+    if (a.msd_bits <= 8)
+        scatter_tile<kMsdRadixMax, kMsdItems, 8>(s, kin, nullptr, id0, cnt, shift, a.msd_bits,
+                                                 goff, ko, io);
+    else if (a.msd_bits == 9)
+        scatter_tile<kMsdRadixMax, kMsdItems, 9>(s, kin, nullptr, id0, cnt, shift, a.msd_bits,
+                                                 goff, ko, io);
+    else
+        scatter_tile<kMsdRadixMax, kMsdItems, 10>(s, kin, nullptr, id0, cnt, shift, a.msd_bits,
+                                                  goff, ko, io);
 }
 
 // ------------------------------------------------- segment sort in LDS

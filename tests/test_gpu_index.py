@@ -84,6 +84,17 @@ def test_head_look_back_over_many_tiles():
     _check(keys, id_base=5)
 
 
+@pytest.mark.parametrize("n", [300_000, 600_000])
+def test_segment_digit_widths_8_and_9(n):
+    """n that give an 8- and a 9-bit segment digit (the scatter's ballot count
+    follows the width), two tables, digests with a heavy key."""
+    g = _rng(13)
+    keys = g.integers(0, 2**63, (2, n), dtype=np.int64).astype(np.uint64) * np.uint64(2) + \
+        g.integers(0, 2, (2, n)).astype(np.uint64)
+    keys[1, ::5] = keys[1, 7]
+    _check(keys)
+
+
 def test_empty_index():
     dev()
     import torch
