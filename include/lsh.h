@@ -190,6 +190,16 @@ lsh_status lsh_index_get_view(const lsh_index *idx, lsh_index_view *view);
 /* Release the host descriptor (device memory belongs to the caller). */
 void lsh_index_free(lsh_index *idx);
 
+/* Consistency counters of the last lsh_build_index that used `workspace`
+ * (same n and L), read back with a copy on `stream` that this call waits for.
+ * counts[0]: parts the big-segment sort could not queue (its stack bound);
+ * counts[1]: look-back waits of the run-head pass that gave up.  Both are
+ * zero by construction; a nonzero value means that build's index is wrong.
+ * EINVAL for a NULL pointer or a workspace smaller than
+ * lsh_build_workspace_bytes(n, L); EHIP if the copy fails. */
+lsh_status lsh_build_check(const void *workspace, size_t ws_bytes, int64_t n, int32_t L,
+                           uint32_t counts[2], void *stream);
+
 /* ------------------------------------------------------------------ query */
 
 /* Answer nq queries against nseg index segments (1..16) with the same L

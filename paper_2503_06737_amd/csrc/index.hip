@@ -1860,6 +1860,37 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     return LSH_OK;
 }
 
+extern "C" lsh_status lsh_build_check(const void *ws, size_t ws_bytes, int64_t n, int32_t L,
+                                      uint32_t counts[2], void *stream)
+{
+    using namespace lsh;
+    if (!counts)
+        LSH_FAIL(LSH_EINVAL, "counts is NULL");
+    counts[0] = counts[1] = 0;
+    if (n < 0 || L < 1)
+        LSH_FAIL(LSH_EINVAL, "bad n=%lld L=%d", (long long)n, L);
+    if (n == 0)
+        return LSH_OK; // no build kernels ran
+    const WsLayout wl = ws_layout(n, L);
+    if (!ws || ws_bytes < wl.total)
+        LSH_FAIL(LSH_EINVAL, "workspace needs %zu bytes, got %zu", wl.total, ws_bytes);
+    const unsigned char *wb = (const unsigned char *)ws;
+    // the same places lsh_build_index gives the counters
+    const uint32_t *overflows = (const uint32_t *)(wb + wl.bcount) + 1;
+    const uint32_t *waits =
+        (const uint32_t *)((const uint64_t *)(wb + wl.hstat) + (size_t)L * wl.nhtiles) +
+        16 * (size_t)L;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(&counts[0], overflows, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&counts[1], waits, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        set_error("lsh_build_check: %s", hip_msg(e));
+        return LSH_EHIP;
+    }
+    return LSH_OK;
+}
+
 extern "C" lsh_status lsh_index_get_view(const lsh_index *idx, lsh_index_view *v)
 {
     if (!idx || !v)

@@ -79,11 +79,12 @@ def lib() -> C.CDLL:
         L.lsh_index_get_view.argtypes = [vp, vp]
         L.lsh_index_free.argtypes = [vp]
         L.lsh_index_free.restype = None
+        L.lsh_build_check.argtypes = [vp, sz, i64, i32, vp, vp]
         L.lsh_query.argtypes = [vp, i32, vp, vp, vp, i64, i32, i64, i32, vp, vp, vp, vp]
         L.lsh_last_error.restype = C.c_char_p
         L.lsh_version.restype = i32
         for fn in ("lsh_hash_cs", "lsh_hash_hcs", "lsh_hash_dense", "lsh_build_index",
-                   "lsh_index_get_view", "lsh_query"):
+                   "lsh_index_get_view", "lsh_query", "lsh_build_check"):
             getattr(L, fn).restype = i32
         _lib = L
     return _lib
@@ -179,8 +180,19 @@ def lsh_hash_dense(x, R, *, family, K, L, w=1.0, b=None, keys=True, codes=False,
 class Index:
     """A built index: its device storage tensor and the library's descriptor."""
 
-    def __init__(self, handle, mem, n, L, id_base):
+    def __init__(self, handle, mem, n, L, id_base, ws=None):
         self.handle, self.mem, self.n, self.L, self.id_base = handle, mem, n, L, id_base
+        self.ws = ws  # the build workspace (kept for check())
+
+    def check(self):
+        """(big-sort stack overflows, run-head waits given up) of this build:
+        both zero unless the build went wrong.  Waits for the build."""
+        if self.ws is None:
+            raise ValueError("the build workspace was not kept")
+        c = (C.c_uint32 * 2)()
+        _check(lib().lsh_build_check(_ptr(self.ws), self.ws.numel(), self.n, self.L, c,
+                                     _stream()))
+        return int(c[0]), int(c[1])
 
     def view(self):
         v = IndexView()
@@ -223,7 +235,7 @@ def lsh_build_index(keys: torch.Tensor, id_base: int = 0, mem: torch.Tensor | No
     _check(lib().lsh_build_index(_ptr(keys) if n else None, keys.stride(0) if n else 0, n, L,
                                  id_base, _ptr(mem), mem.numel(), _ptr(ws), ws.numel(),
                                  C.byref(h), _stream()))
-    return Index(h, mem, n, L, id_base)
+    return Index(h, mem, n, L, id_base, ws)
 
 
 def lsh_query(segs, base, Q, qkeys, *, k, watermark=None, metric=E2LSH, base_scale=None,

@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 def _check(keys, id_base=0):
     ref = oracle.build_index(keys, id_base)
     idx = lsh.lsh_build_index(to_dev(keys), id_base=id_base)
+    assert idx.check() == (0, 0)
     sid, uk, of, nu = idx.arrays()
     L, n = keys.shape
     nu = to_host(nu)
