@@ -43,10 +43,9 @@
 
 namespace lsh {
 
-// RB: consecutive rows a workgroup hashes before it writes their keys (32
-// or 64: a table's RB keys fill two or four 128-byte lines)
+// RB: consecutive rows a workgroup hashes before it writes their keys; a
+// table's RB keys fill two 128-byte lines
 constexpr int kRowsPerBlock = 32;
-constexpr int kRowsPerBlockWide = 64;
 constexpr int kMaxModes = 8;
 
 __host__ __device__ constexpr int align16(int v) { return (v + 15) & ~15; }
@@ -59,7 +58,6 @@ __host__ __device__ constexpr int bin_pos(int l) { return l + (l >> 4); }
 constexpr int kTrashSlots = kWave;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 struct HashArgs {
     const void *x;
@@ -93,7 +91,7 @@ struct HashArgs {
     // layout
     int32_t waves;       // waves per workgroup
     int32_t mpad;        // bin slots per wave (bins, pad words, trash), multiple of 4
-    int32_t wave_region; // LDS bytes per wave region (>= 4 * mpad; a power of two unless the table is in registers)
+    int32_t wave_region; // LDS bytes per wave region: a power of two >= 4 * mpad
     int32_t tab_entries; // table entries: 64 * CH * VEC * pieces (rows padded to whole chunks)
     int32_t tab_off, bl_off, hinit_off, mask_off; // LDS byte offsets
     // key staging (stage_stride 0: keys are stored straight to memory):
@@ -102,21 +100,13 @@ struct HashArgs {
     //            + ((t & (2^stage_tpc_log2 - 1)) * (RB + 1) + i) * 8
     int32_t stage_base, stage_stride, stage_tpc_log2;
     int32_t pieces; // long rows: pieces of 64 * CH chunks per row (even); 1 otherwise
-    int32_t rb;     // rows per block: kRowsPerBlock or kRowsPerBlockWide
 };
-
-// A lane keeps the table entries of its chunks in registers for the whole
-// kernel (rows read whole, at most 16 entries per lane).
-__host__ __device__ constexpr bool tab_in_regs(int ch, int vec, bool long_rows)
-{
-    return !long_rows && ch * vec <= 16;
-}
 
 __device__ __forceinline__ uint32_t stage_addr(const HashArgs &a, int t, int slot)
 {
     const uint32_t tpc_mask = (1u << a.stage_tpc_log2) - 1u;
     return (uint32_t)a.stage_base + ((uint32_t)t >> a.stage_tpc_log2) * (uint32_t)a.stage_stride +
-           (((uint32_t)t & tpc_mask) * (uint32_t)(a.rb + 1) + (uint32_t)slot) * 8u;
+           (((uint32_t)t & tpc_mask) * (kRowsPerBlock + 1) + (uint32_t)slot) * 8u;
 }
 
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
@@ -169,11 +159,8 @@ __device__ __forceinline__ uint32_t table_bin(const HashArgs &a, int32_t j, bool
 }
 
 // LDS table entry of coordinate j: byte offset of its bin's slot inside a
-// wave's region, sign in bit 31.  With the table in LDS a lane forms the LDS
-// address of the slot with one v_and_or (offset bits | its wave's region
-// base, regions being a power of two in size); with the entries in registers
-// the address (offset + region base) is formed once per kernel, and regions
-// need no padding.
+// wave's region, sign in bit 31.  A lane forms the LDS address of the slot
+// with one v_and_or (offset bits | its wave's region base).
 __device__ __forceinline__ uint32_t table_entry(const HashArgs &a, int32_t j, bool &bad)
 {
     uint32_t neg;
@@ -685,13 +672,7 @@ void hash_kernel(HashArgs a)
 
     // ---- rows owned by this wave
     const int32_t nchunk = a.d / VEC; // d % VEC == 0 when ALIGNED
-    // row buffers in flight (short rows)
-    constexpr int NB = 2;
-    constexpr bool kTabRegs = tab_in_regs(CH, VEC, LONG);
     const uint32_t offmask = (uint32_t)a.wave_region - 1u;
-    auto slot_addr = [&](uint32_t ent) {
-        return kTabRegs ? (ent & 0x7fffffffu) + region : (ent & offmask) | region;
-    };
 
     unsigned nflag = 0, nchg = 0, nsat = 0;
 
@@ -737,6 +718,7 @@ void hash_kernel(HashArgs a)
             }
         }
     };
+    constexpr bool kTabRegs = !LONG && CH * VEC <= 16;
     uint32_t treg[kTabRegs ? CH * VEC : 1];
     if constexpr (kTabRegs) {
 #pragma unroll
@@ -804,7 +786,7 @@ void hash_kernel(HashArgs a)
                 const uint32_t ent = tw[e2];
                 const float v = chunk_value<DT, ALIGNED>(buf[i], e2);
                 const float sv = __uint_as_float(__float_as_uint(v) ^ (ent & 0x80000000u));
-                lds_add_i32(slot_addr(ent), (int32_t)ldexpf(sv, k));
+                lds_add_i32((ent & offmask) | region, (int32_t)ldexpf(sv, k));
             }
         };
         if constexpr (kTabRegs) {
@@ -876,7 +858,7 @@ void hash_kernel(HashArgs a)
                 const uint32_t ent = tw[i & 1][e2];
                 const float v = chunk_value<DT, ALIGNED>(buf[i], e2);
                 const float sv = __uint_as_float(__float_as_uint(v) ^ (ent & 0x80000000u));
-                lds_add_i32(slot_addr(ent), (int32_t)ldexpf(sv, k));
+                lds_add_i32((ent & offmask) | region, (int32_t)ldexpf(sv, k));
             }
         }
     };
@@ -886,117 +868,70 @@ void hash_kernel(HashArgs a)
     // by the grid; wave w of the workgroup takes rows w, w + waves, ... of
     // each block, so all waves of the GPU read one contiguous window of X
     // that slides forward.  The keys of a block are staged in LDS and, after
-    // a workgroup barrier, written as RB * 8-byte runs per table, 16 bytes
-    // per lane and non-temporal: storing each row's L keys straight from the
-    // lanes would touch L pages and L lines per instruction.
-    // Every load is unconditional: rows past the end re-read row n - 1.  The
-    // cursors are kept in 32-bit scalars (n < 2^30 is checked on the host).
-    // Every wave runs every block of its workgroup, so the barriers are
-    // uniform.
+    // a workgroup barrier, written as 256-byte runs per table (one store
+    // instruction covers two tables): storing each row's L keys straight
+    // from the lanes would touch L pages and L lines per instruction.
+    // Row r' (the wave's next) is loaded before row r is processed (two
+    // register buffers, alternated by unrolling the loop twice: RB / waves
+    // is even); every load is unconditional, rows past the end re-read row
+    // n - 1.  The cursor is kept in 32-bit scalars (n < 2^30 is checked on
+    // the host).  Every wave runs every block of its workgroup, so the
+    // barriers are uniform.
     const int32_t n32 = (int32_t)a.n;
-    const int32_t rb = a.rb;
-    const int32_t rb_log2 = rb == kRowsPerBlockWide ? 6 : 5;
-    const int32_t per_wave = rb / a.waves;
-    const int32_t nblk = (n32 + rb - 1) / rb;
-    const int32_t grid = (int32_t)gridDim.x;
+    const int32_t per_wave = kRowsPerBlock / a.waves;
+    const int32_t nblk = (n32 + kRowsPerBlock - 1) / kRowsPerBlock;
     const bool staged = a.keys && a.stage_stride;
     auto first_row = [&](int32_t b) {
-        return __builtin_amdgcn_readfirstlane(b * rb + wid);
+        return __builtin_amdgcn_readfirstlane(b * kRowsPerBlock + wid);
     };
     auto clamp_row = [&](int32_t r) { return r < n32 ? r : n32 - 1; };
-    // keys 16-byte aligned in every table: a thread stores two at once
-    const bool pairs = ((uintptr_t)a.keys & 15u) == 0 && (a.key_ld & 1) == 0;
-    auto flush_block = [&](int32_t base) {
-        if (staged) {
-            __syncthreads();
-            if (pairs) {
-                const int32_t total = a.L << (rb_log2 - 1);
-                for (int32_t q = tid; q < total; q += (int32_t)blockDim.x) {
-                    const int32_t t = q >> (rb_log2 - 1), i = 2 * (q & ((rb >> 1) - 1));
-                    const uint64_t k0 = *(const lds_u64 *)(size_t)stage_addr(a, t, i);
-                    const uint64_t k1 = *(const lds_u64 *)(size_t)stage_addr(a, t, i + 1);
-                    uint64_t *dst = a.keys + (int64_t)t * a.key_ld + base + i;
-                    if (base + i + 1 < n32)
-                        __builtin_nontemporal_store(u64x2{k0, k1}, (u64x2 *)dst);
-                    else if (base + i < n32)
-                        *dst = k0;
-                }
-            } else {
-                const int32_t total = a.L << rb_log2;
-                for (int32_t q = tid; q < total; q += (int32_t)blockDim.x) {
-                    const int32_t t = q >> rb_log2, i = q & (rb - 1);
-                    if (base + i < n32)
-                        a.keys[(int64_t)t * a.key_ld + base + i] =
-                            *(const lds_u64 *)(size_t)stage_addr(a, t, i);
-                }
-            }
-            __syncthreads();
-        }
-    };
     int32_t blk = (int32_t)blockIdx.x;
     int32_t r0 = first_row(blk);
-
-    if constexpr (!LONG) {
-        // A ring of NB row buffers: the wave's rows form one sequence over its
-        // blocks, and row s is summed while rows s + 1 .. s + NB - 1 are in
-        // flight.  NB divides RB / waves (waves <= 8), so every block starts
-        // at buffer 0 and the ring index is a constant after unrolling.
-        static_assert((kRowsPerBlock / 8) % NB == 0 && (kRowsPerBlockWide / 8) % NB == 0,
-                      "NB must divide the rows per wave");
-        Buf buf[NB];
-        int32_t lblk = blk, lrow = r0, lj = 0; // next row to load
-        auto load_next = [&](Buf &b) {
-            load_row(b, clamp_row(lrow));
-            if (++lj < per_wave) {
-                lrow += a.waves;
-            } else {
-                lj = 0;
-                lblk += grid;
-                lrow = first_row(lblk);
-            }
-        };
-#pragma unroll
-        for (int u = 0; u + 1 < NB; ++u)
-            load_next(buf[u]);
-        for (; blk < nblk; blk += grid) {
-            const int32_t base = blk * rb;
-            for (int32_t j = 0; j < per_wave; j += NB) {
-#pragma unroll
-                for (int u = 0; u < NB; ++u) {
-                    load_next(buf[(u + NB - 1) % NB]);
-                    const int32_t r = base + wid + (j + u) * a.waves;
-                    if (r < n32)
-                        process_row(buf[u], r, r - base);
-                }
-            }
-            flush_block(base);
-        }
-    } else {
-        // long rows: pieces alternate between two buffers (a.pieces is even,
+    Buf bufA, bufB;
+    load_row(bufA, clamp_row(r0));
+    for (; blk < nblk; blk += (int32_t)gridDim.x) {
+        const int32_t base = blk * kRowsPerBlock;
+        // long rows: pieces alternate between the buffers (a.pieces is even,
         // so every row starts in bufA); the next row's first piece is loaded
         // during the current row's last one
-        Buf bufA, bufB;
-        load_row(bufA, clamp_row(r0));
-        for (; blk < nblk; blk += grid) {
-            const int32_t base = blk * rb;
-            for (int32_t j = 0; j < per_wave; ++j) {
-                const int32_t rn = j + 1 < per_wave ? r0 + a.waves : first_row(blk + grid);
-                for (int32_t p = 0; p < a.pieces; p += 2) {
-                    load_row(bufB, clamp_row(r0), p + 1);
-                    if (r0 < n32)
-                        piece(bufA, p);
-                    if (p + 2 < a.pieces)
-                        load_row(bufA, clamp_row(r0), p + 2);
-                    else
-                        load_row(bufA, clamp_row(rn), 0);
-                    if (r0 < n32)
-                        piece(bufB, p + 1);
-                }
+        for (int32_t j = 0; LONG && j < per_wave; ++j) {
+            const int32_t rn = j + 1 < per_wave ? r0 + a.waves : first_row(blk + (int32_t)gridDim.x);
+            for (int32_t p = 0; p < a.pieces; p += 2) {
+                load_row(bufB, clamp_row(r0), p + 1);
                 if (r0 < n32)
-                    finish_row(r0, r0 - base, koff - e_cur, e_cur, mb_row, nres);
-                r0 = rn;
+                    piece(bufA, p);
+                if (p + 2 < a.pieces)
+                    load_row(bufA, clamp_row(r0), p + 2);
+                else
+                    load_row(bufA, clamp_row(rn), 0);
+                if (r0 < n32)
+                    piece(bufB, p + 1);
             }
-            flush_block(base);
+            if (r0 < n32)
+                finish_row(r0, r0 - base, koff - e_cur, e_cur, mb_row, nres);
+            r0 = rn;
+        }
+        for (int32_t j = 0; !LONG && j < per_wave; j += 2) {
+            const int32_t r1 = r0 + a.waves;
+            load_row(bufB, clamp_row(r1));
+            if (r0 < n32)
+                process_row(bufA, r0, r0 - base);
+            const int32_t r2 = j + 2 < per_wave ? r1 + a.waves : first_row(blk + (int32_t)gridDim.x);
+            load_row(bufA, clamp_row(r2));
+            if (r1 < n32)
+                process_row(bufB, r1, r1 - base);
+            r0 = r2;
+        }
+        if (staged) {
+            __syncthreads();
+            const int32_t total = a.L * kRowsPerBlock;
+            for (int32_t q = tid; q < total; q += (int32_t)blockDim.x) {
+                const int32_t t = q / kRowsPerBlock, i = q % kRowsPerBlock;
+                if (base + i < n32)
+                    a.keys[(int64_t)t * a.key_ld + base + i] =
+                        *(const lds_u64 *)(size_t)stage_addr(a, t, i);
+            }
+            __syncthreads();
         }
     }
 
@@ -1285,18 +1220,17 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         a.pieces += a.pieces & 1;
     }
 
-    // LDS layout: per-wave regions, then the shared table and constants.
-    // Regions are a power of two in size (a slot's address is offset |
-    // region base) unless the table entries stay in registers.
+    // LDS layout: per-wave regions of a power-of-two size (so a slot's
+    // address is offset | region base), then the shared table and constants
     a.mpad = (int32_t)align_up((size_t)bin_pos(a.m) + kTrashSlots, 4);
-    const int vec = al ? per16 : 1;
-    a.tab_entries = 64 * ch * vec * a.pieces;
-    const bool tregs = tab_in_regs(ch, vec, a.pieces > 1);
     int region = 256;
     while (region < a.mpad * 4)
         region <<= 1;
-    a.rb = kRowsPerBlock;
+    a.wave_region = region;
+    const int vec = al ? per16 : 1;
+    a.tab_entries = 64 * ch * vec * a.pieces;
     const size_t lds_max = 160 * 1024;
+    const int64_t nblk = (pts->n + kRowsPerBlock - 1) / kRowsPerBlock;
     const size_t masks = (size_t)((a.m + 63) / 64) * 8;
     // key staging: ceil(L / waves) tables (rounded up to a power of two) per
     // chunk of RB + 1 keys each, chunk c in the unused tail of wave c's
@@ -1309,7 +1243,7 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         int lg = 0;
         while ((1 << lg) * wv < a.L)
             ++lg;
-        const size_t chunk = (size_t)(1 << lg) * (size_t)(a.rb + 1) * 8;
+        const size_t chunk = (size_t)(1 << lg) * (kRowsPerBlock + 1) * 8;
         const size_t nchunk = (size_t)((a.L + (1 << lg) - 1) >> lg);
         a.stage_tpc_log2 = lg;
         if ((size_t)region - (size_t)a.mpad * 4 >= chunk) {
@@ -1339,35 +1273,16 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         a.mask_off = (int32_t)mo;
         return off;
     };
-    // First choice, with the entries in registers and keys staged: blocks of
-    // 64 rows (longer runs per table, half the barriers per row) and regions
-    // packed end to end, taken when eight waves still leave room for two
-    // workgroups per CU.  Otherwise 32-row blocks; more waves per workgroup
-    // amortise the table, fewer fit more workgroups.
+    // more waves per workgroup amortise the table; fewer fit more workgroups
     int waves = 8;
-    bool wide = false;
-    if (tregs && stage_on) {
-        const int pow2 = region;
-        a.rb = kRowsPerBlockWide;
-        region = (int)align_up((size_t)a.mpad * 4, 256);
-        wide = lds_for(waves) <= lds_max / 2 && (pts->n + a.rb - 1) / a.rb >= waves;
-        if (!wide) {
-            a.rb = kRowsPerBlock;
-            region = pow2;
-        }
-    }
-    const int64_t nblk = (pts->n + a.rb - 1) / a.rb;
-    if (!wide) {
+    while (waves > 1 && (lds_for(waves) > lds_max || waves > nblk))
+        waves >>= 1;
+    if (lds_for(waves) > lds_max && stage_on) {
+        stage_on = false; // keys too many to stage: store them directly
+        waves = 8;
         while (waves > 1 && (lds_for(waves) > lds_max || waves > nblk))
             waves >>= 1;
-        if (lds_for(waves) > lds_max && stage_on) {
-            stage_on = false; // keys too many to stage: store them directly
-            waves = 8;
-            while (waves > 1 && (lds_for(waves) > lds_max || waves > nblk))
-                waves >>= 1;
-        }
     }
-    a.wave_region = region;
     size_t lds = lds_for(waves);
     if (lds > lds_max)
         LSH_FAIL(LSH_EINVAL, "d=%d, m=%d, L=%d need %zu bytes of LDS (max %zu)", pts->d, a.m, a.L,
