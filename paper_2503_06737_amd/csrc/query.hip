@@ -16,6 +16,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "lsh_internal.h"
 
 namespace lsh {
@@ -56,6 +58,7 @@ struct QueryArgs {
     int32_t k;
     uint32_t watermark; // ids >= watermark are ignored (clamped to 2^32-1)
     int32_t metric;
+    int32_t vec4; // FP32 base rows read as 16-byte chunks (aligned, d % 4 == 0)
     int64_t *ids;
     float *score;
     int32_t *ncand;
@@ -130,6 +133,59 @@ __device__ __forceinline__ void score_rows(const QueryArgs &a, const float *qv,
                 } else {
                     acc[r] = fmaf(qj, x, acc[r]);
                     xx[r] = fmaf(x, x, xx[r]);
+                }
+            }
+        }
+    }
+}
+
+// The same sums for FP32 rows read as 16-byte chunks (the base pointer
+// 16-byte aligned, ld and d multiples of 4): 4 chunk loads per lane and row
+// cover 1024 elements, so a wave keeps NR = 8 rows in flight within the
+// 63 loads a wave can have outstanding.  Chunk indexes are clamped into the
+// row; the lanes past its end add 0.
+constexpr int kScoreChunks = 4;
+constexpr int kScoreRowsV4 = 6;
+
+template <int NR>
+__device__ __forceinline__ void score_rows_v4(const QueryArgs &a, const float *qv,
+                                              const int64_t (&row)[NR], float (&acc)[NR],
+                                              float (&xx)[NR])
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int lane = lane_id();
+    const int nch = a.d >> 2;
+    const f4 *rp[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        rp[r] = (const f4 *)((const float *)a.bx + row[r] * a.bld);
+        acc[r] = 0.0f;
+        xx[r] = 0.0f;
+    }
+    for (int c0 = 0; c0 < nch; c0 += kScoreChunks * kWave) {
+        f4 xv[NR][kScoreChunks];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int u = 0; u < kScoreChunks; ++u)
+                xv[r][u] = rp[r][min(c0 + u * kWave + lane, nch - 1)];
+#pragma unroll
+        for (int u = 0; u < kScoreChunks; ++u) {
+            const int c = c0 + u * kWave + lane;
+            const bool in = c < nch;
+            const f4 qc = in ? *(const f4 *)(qv + 4 * c) : f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const f4 x = in ? xv[r][u] : f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (a.metric == LSH_E2LSH) {
+                        const float df = qc[e] - x[e];
+                        acc[r] = fmaf(df, df, acc[r]);
+                    } else {
+                        acc[r] = fmaf(qc[e], x[e], acc[r]);
+                        xx[r] = fmaf(x[e], x[e], xx[r]);
+                    }
                 }
             }
         }
@@ -246,7 +302,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, u
     return off + incl - v;
 }
 
-__global__ __launch_bounds__(kQThreads) void query_kernel(QueryArgs a)
+__global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) void query_kernel(QueryArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     float *qv = (float *)lds;                                          // [d]
@@ -419,34 +475,52 @@ __global__ __launch_bounds__(kQThreads) void query_kernel(QueryArgs a)
         }
         __syncthreads();
         const uint32_t uc = s_ucount;
-        // score: a wave takes candidates c and c + kQWaves together (their
-        // loads overlap); the second one repeats the first past the end
-        for (uint32_t c = wid; c < uc; c += 2 * kQWaves) {
-            const bool two = c + kQWaves < uc;
-            const int64_t row[2] = {cand[c], cand[two ? c + kQWaves : c]};
-            float acc[2], xx[2];
-            if (a.bdt == LSH_F32)
-                score_rows<LSH_F32, 2>(a, qv, row, acc, xx);
-            else if (a.bdt == LSH_BF16)
-                score_rows<LSH_BF16, 2>(a, qv, row, acc, xx);
-            else
-                score_rows<LSH_FP8_E4M3FN, 2>(a, qv, row, acc, xx);
+        // score: a wave takes NR candidates c, c + kQWaves, ... together
+        // (their loads overlap); those past the end repeat c
+        auto score_all = [&](auto nr_tag, auto scorer) {
+            constexpr int NR = decltype(nr_tag)::value;
+            for (uint32_t c = wid; c < uc; c += NR * kQWaves) {
+                int64_t row[NR];
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const float ac = wave_sum(acc[r]), xs = wave_sum(xx[r]);
-                float sc;
-                if (a.metric == LSH_E2LSH) {
-                    sc = sqrtf(ac);
-                } else {
-                    const float xn = sqrtf(xs);
-                    const float cs = (qn > 0.0f && xn > 0.0f) ? ac / (qn * xn) : 0.0f;
-                    sc = 1.0f - cs;
+                for (int r = 0; r < NR; ++r)
+                    row[r] = cand[c + r * kQWaves < uc ? c + r * kQWaves : c];
+                float acc[NR], xx[NR];
+                scorer(row, acc, xx);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const float ac = wave_sum(acc[r]), xs = wave_sum(xx[r]);
+                    float sc;
+                    if (a.metric == LSH_E2LSH) {
+                        sc = sqrtf(ac);
+                    } else {
+                        const float xn = sqrtf(xs);
+                        const float cs = (qn > 0.0f && xn > 0.0f) ? ac / (qn * xn) : 0.0f;
+                        sc = 1.0f - cs;
+                    }
+                    if (lane == 0 && c + r * kQWaves < uc)
+                        sbuf[c + r * kQWaves] =
+                            ((uint64_t)__float_as_uint(fmaxf(sc, 0.0f)) << 32) | (uint64_t)row[r];
                 }
-                if (lane == 0 && (r == 0 || two))
-                    sbuf[c + r * kQWaves] =
-                        ((uint64_t)__float_as_uint(fmaxf(sc, 0.0f)) << 32) | (uint64_t)row[r];
             }
-        }
+        };
+        using nrv = std::integral_constant<int, kScoreRowsV4>;
+        using nr2 = std::integral_constant<int, 2>;
+        if (a.vec4)
+            score_all(nrv{}, [&](const int64_t (&row)[kScoreRowsV4], float (&acc)[kScoreRowsV4], float (&xx)[kScoreRowsV4]) {
+                score_rows_v4<kScoreRowsV4>(a, qv, row, acc, xx);
+            });
+        else if (a.bdt == LSH_F32)
+            score_all(nr2{}, [&](const int64_t (&row)[2], float (&acc)[2], float (&xx)[2]) {
+                score_rows<LSH_F32, 2>(a, qv, row, acc, xx);
+            });
+        else if (a.bdt == LSH_BF16)
+            score_all(nr2{}, [&](const int64_t (&row)[2], float (&acc)[2], float (&xx)[2]) {
+                score_rows<LSH_BF16, 2>(a, qv, row, acc, xx);
+            });
+        else
+            score_all(nr2{}, [&](const int64_t (&row)[2], float (&acc)[2], float (&xx)[2]) {
+                score_rows<LSH_FP8_E4M3FN, 2>(a, qv, row, acc, xx);
+            });
         __syncthreads();
         // merge with the running top-k
         const int kc = s_kcur;
@@ -560,6 +634,8 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
     a.k = k;
     a.watermark = (uint32_t)wm;
     a.metric = metric;
+    a.vec4 = base->dtype == LSH_F32 && ((uintptr_t)base->x & 15u) == 0 && base->ld % 4 == 0 &&
+             Q->d % 4 == 0;
     a.ids = ids;
     a.score = score;
     a.ncand = ncand;

@@ -29,8 +29,9 @@ def _compare(ids, sc, nc, rids, rsc, rnc, what=""):
     return swaps
 
 
-def _pipeline(x, Q, h, s, b, K, L, w, family, segs_split=None, watermark=None, k=10):
-    xd = to_dev(x)
+def _pipeline(x, Q, h, s, b, K, L, w, family, segs_split=None, watermark=None, k=10, ld_pad=0):
+    # ld_pad: the base rows sit in a wider array (row stride d + ld_pad)
+    xd = to_dev(np.pad(x, ((0, 0), (0, ld_pad))))[:, :x.shape[1]] if ld_pad else to_dev(x)
     Qd = to_dev(Q)
     kw = dict(family=family, K=K, L=L, w=w, b=to_dev(b))
     keys = lsh.lsh_hash_cs(xd, to_dev(h), to_dev(s), recheck=True, **kw)["keys"]
@@ -76,6 +77,23 @@ def test_query_segments_and_watermark():
     got, ref = _pipeline(x, Q, h, s, b, 8, 8, 8.0, oracle.SRP, segs_split=[2500, 4000, 6000],
                          watermark=5000, k=17)
     _compare(*got, *ref, what="segments")
+
+
+@pytest.mark.parametrize("d,ld_pad,family,w", [(50, 0, oracle.E2LSH, 8.0), (256, 1, oracle.SRP, 8.0),
+                                                (1500, 0, oracle.SRP, 8.0),
+                                                (1500, 0, oracle.E2LSH, 64.0)])
+def test_query_score_paths(d, ld_pad, family, w):
+    """FP32 re-rank on both scoring paths: rows read as 16-byte chunks (d and
+    the row stride multiples of 4; d = 1500 takes two passes of 1024) and
+    element by element (d = 50; row stride 257)."""
+    dev()
+    x = synth.gaussian_clusters(4000, d, 8, 0.2, 51 + d)
+    Q = synth.gaussian_clusters(100, d, 8, 0.2, 51 + d, stream=1)
+    h, s = synth.cs_state(d, 64, 52)
+    b = synth.shifts(64, w, 52)
+    got, ref = _pipeline(x, Q, h, s, b, 8, 8, w, family, k=10, ld_pad=ld_pad)
+    assert (to_host(got[2]) > 0).mean() > 0.9  # the scoring path is exercised
+    _compare(*got, *ref, what=f"d={d} ld_pad={ld_pad}")
 
 
 def test_query_one_bucket_is_exact_knn_with_windows():
