@@ -303,13 +303,24 @@ def serving(torch, synth, dev, wl, X, hd, sd, bd):
             return pool[lo:lo + m]
         return take
 
+    def server(reqs):
+        cap = X.shape[0] + sum(r.points.shape[0] for r in reqs if r.kind == "insert")
+        return serve.Server(X, hd, sd, bd, K=wl.K, L=wl.L, w=wl.w, capacity=cap,
+                            budget_bytes=2 << 30, k=10)
+
     out = {}
     for name, rate, n_req in (("sustained", 600.0, 1200), ("planned_overload", 50_000.0, 800)):
+        # warm-up, not measured: a server of the same configuration serves a
+        # short stream of its own (device and pinned-memory allocator caches,
+        # kernel set-up); the measured server then starts from that state
+        wreqs = serve.poisson_stream(n_req // 4, rate, 0.9, 4096, wl.d, src(qpool, "q"),
+                                     src(ipool, "i"), wl.seed + 4)
+        wsrv = server(wreqs)
+        wsrv.serve(wreqs, realtime=True)
+        del wsrv
         reqs = serve.poisson_stream(n_req, rate, 0.9, 4096, wl.d, src(qpool, "q"),
                                     src(ipool, "i"), wl.seed + 3)
-        cap = X.shape[0] + sum(r.points.shape[0] for r in reqs if r.kind == "insert")
-        srv = serve.Server(X, hd, sd, bd, K=wl.K, L=wl.L, w=wl.w, capacity=cap,
-                           budget_bytes=2 << 30, k=10)
+        srv = server(reqs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = srv.serve(reqs, realtime=True)
