@@ -22,8 +22,11 @@
 
 namespace lsh {
 
+// Threads per query: 512 when the batch has at most one query per CU (a
+// query then has a CU to itself), else 256 (two queries per CU: the LDS
+// limit).
 constexpr int kQThreads = 256;
-constexpr int kQWaves = kQThreads / kWave;
+constexpr int kQThreadsSolo = 512;
 constexpr int kCap = 2048;        // (bucket, id) entries per window
 constexpr int kMaxK = 64;
 constexpr int kSortCap = 4096;    // >= next pow2 of kCap + kMaxK
@@ -265,6 +268,72 @@ __device__ void block_bitonic(uint64_t *s, int n)
     }
 }
 
+// The same sort by one wave in registers, for n <= 256 keys: element e =
+// 4 * lane + r is v[r] of the lane (keys past n sort last as ~0).  The
+// network always spans 256 elements; the steps with j >= 4 exchange with
+// lane ^ (j / 4), the others within the lane, and none needs a workgroup
+// barrier.
+__device__ __forceinline__ void wave_bitonic256(uint64_t *s, int n)
+{
+    const int lane = lane_id();
+    uint64_t v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = 4 * lane + r;
+        v[r] = e < n ? s[e] : ~0ull;
+    }
+#pragma unroll
+    for (int k = 2; k <= 4 * kWave; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 4) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = 4 * lane + r;
+                    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v[r], j >> 2, kWave);
+                    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v[r] >> 32), j >> 2, kWave);
+                    const uint64_t y = ((uint64_t)hi << 32) | lo;
+                    const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+                    const bool y_less = y < v[r];
+                    v[r] = keep_min == y_less ? y : v[r];
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if ((r & j) == 0) {
+                        const bool asc = ((4 * lane + r) & k) == 0;
+                        const uint64_t x = v[r], y = v[r | j];
+                        const bool swap = asc ? (y < x) : (x < y);
+                        v[r] = swap ? y : x;
+                        v[r | j] = swap ? x : y;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = 4 * lane + r;
+        if (e < n)
+            s[e] = v[r];
+    }
+}
+
+// Ascending sort of n (a power of two) keys in LDS: the first wave alone
+// when n <= 256, else the whole block.  Every thread calls; ends with a
+// workgroup barrier.
+__device__ __forceinline__ void sort_keys(uint64_t *s, int n)
+{
+    if (n <= 4 * kWave) {
+        if (threadIdx.x < kWave)
+            wave_bitonic256(s, n);
+        __syncthreads();
+    } else {
+        block_bitonic(s, n);
+    }
+}
+
+template <int QW>
 __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *red)
 {
     v = wave_sum(v);
@@ -272,13 +341,14 @@ __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *red)
         red[threadIdx.x / kWave] = v;
     __syncthreads();
     uint32_t t = 0;
-    for (int w = 0; w < kQWaves; ++w)
+    for (int w = 0; w < QW; ++w)
         t += red[w];
     __syncthreads();
     return t;
 }
 
 // Exclusive prefix of v over the block (thread order); *total gets the sum.
+template <int QW>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, uint32_t *total)
 {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
@@ -293,7 +363,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, u
         red[wid] = incl;
     __syncthreads();
     uint32_t off = 0, tot = 0;
-    for (int w = 0; w < kQWaves; ++w) {
+    for (int w = 0; w < QW; ++w) {
         off += w < wid ? red[w] : 0;
         tot += red[w];
     }
@@ -302,8 +372,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, u
     return off + incl - v;
 }
 
-__global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) void query_kernel(QueryArgs a)
+template <int QT>
+__global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(2))) void query_kernel(QueryArgs a)
 {
+    constexpr int QW = QT / kWave;
     extern __shared__ __align__(16) unsigned char lds[];
     float *qv = (float *)lds;                                          // [d]
     uint32_t *lst_start = (uint32_t *)(lds + ((a.d * 4 + 15) & ~15));  // [kMaxLists]
@@ -314,7 +386,7 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     uint64_t *sbuf = (uint64_t *)(((uintptr_t)(lst_take + kMaxLists) + 15) & ~(uintptr_t)15); // [kSortCap]
     uint64_t *topk = sbuf + kSortCap;                                  // [kMaxK]
     uint32_t *cand = (uint32_t *)(topk + kMaxK);                       // [kCap]
-    __shared__ uint32_t red[kQWaves];
+    __shared__ uint32_t red[QW];
     __shared__ float s_qnorm;
     __shared__ int s_kcur;
     __shared__ uint32_t s_ncand, s_hi, s_wcount, s_ucount;
@@ -325,7 +397,7 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
 
     // query row -> LDS, and its norm
     float part = 0.0f;
-    for (int j = tid; j < a.d; j += kQThreads) {
+    for (int j = tid; j < a.d; j += QT) {
         float v = load_val(a.qx, a.qdt, a.qscale, q, a.qld, j);
         qv[j] = v;
         part += v * v;
@@ -336,7 +408,7 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     __syncthreads();
     if (tid == 0) {
         float t = 0.0f;
-        for (int w = 0; w < kQWaves; ++w)
+        for (int w = 0; w < QW; ++w)
             t += __uint_as_float(red[w]);
         s_qnorm = sqrtf(t);
         s_kcur = 0;
@@ -344,7 +416,7 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     }
 
     // probe: bucket of the query key in every (segment, table)
-    for (int li = tid; li < nl; li += kQThreads) {
+    for (int li = tid; li < nl; li += QT) {
         int sg = li / a.L, t = li % a.L;
         const QSeg &S = a.seg[sg];
         uint64_t key = a.qkeys[(int64_t)t * a.qkey_ld + q];
@@ -371,9 +443,9 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     while (true) {
         // remaining entries
         uint32_t rem = 0;
-        for (int li = tid; li < nl; li += kQThreads)
+        for (int li = tid; li < nl; li += QT)
             rem += lst_end[li] - lst_cur[li];
-        rem = block_sum_u32(rem, red);
+        rem = block_sum_u32<QW>(rem, red);
         if (rem == 0)
             break;
         // window [.., hi): all remaining if they fit, else the largest id bound
@@ -386,12 +458,12 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
             while (hi_v - lo_v > 1) {
                 uint32_t mid = lo_v + ((hi_v - lo_v) >> 1);
                 uint32_t c = 0;
-                for (int li = tid; li < nl; li += kQThreads) {
+                for (int li = tid; li < nl; li += QT) {
                     int sg = li / a.L, t = li % a.L;
                     const uint32_t *ids = a.seg[sg].ids + (int64_t)t * a.seg[sg].n;
                     c += lower_bound_u32(ids, lst_cur[li], lst_end[li], mid) - lst_cur[li];
                 }
-                c = block_sum_u32(c, red);
+                c = block_sum_u32<QW>(c, red);
                 if (c <= kCap)
                     lo_v = mid;
                 else
@@ -402,7 +474,7 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
             __syncthreads();
         }
         const uint32_t hiv = s_hi;
-        for (int li = tid; li < nl; li += kQThreads) {
+        for (int li = tid; li < nl; li += QT) {
             int sg = li / a.L, t = li % a.L;
             const uint32_t *ids = a.seg[sg].ids + (int64_t)t * a.seg[sg].n;
             uint32_t e = hiv == 0xffffffffu ? lst_end[li]
@@ -412,13 +484,13 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
         __syncthreads();
         {
             // prefix of the per-list counts: thread owns a contiguous run of lists
-            const int per = (nl + kQThreads - 1) / kQThreads;
+            const int per = (nl + QT - 1) / QT;
             const int l0 = tid * per, l1 = l0 + per < nl ? l0 + per : nl;
             uint32_t mine = 0;
             for (int li = l0; li < l1; ++li)
                 mine += lst_take[li];
             uint32_t tot;
-            uint32_t run = block_excl_scan(mine, red, &tot);
+            uint32_t run = block_excl_scan<QW>(mine, red, &tot);
             for (int li = l0; li < l1; ++li) {
                 lst_pre[li] = run;
                 run += lst_take[li];
@@ -434,7 +506,7 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
         while (p2 < (int)wc)
             p2 <<= 1;
         // gather the window's ids
-        for (uint32_t e = tid; e < (uint32_t)p2; e += kQThreads) {
+        for (uint32_t e = tid; e < (uint32_t)p2; e += QT) {
             uint64_t v = ~0ull;
             if (e < wc) {
                 int lo = 0, hi = nl; // list holding entry e: last li with pre[li] <= e
@@ -453,18 +525,18 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
             sbuf[e] = v;
         }
         __syncthreads();
-        for (int li = tid; li < nl; li += kQThreads)
+        for (int li = tid; li < nl; li += QT)
             lst_cur[li] += lst_take[li];
-        block_bitonic(sbuf, p2);
+        sort_keys(sbuf, p2);
         {
             // distinct ids, compacted in order: thread owns a contiguous run
-            const int per = (p2 + kQThreads - 1) / kQThreads;
+            const int per = (p2 + QT - 1) / QT;
             const int e0 = tid * per, e1 = e0 + per < (int)wc ? e0 + per : (int)wc;
             uint32_t mine = 0;
             for (int e = e0; e < e1; ++e)
                 mine += (e == 0 || sbuf[e] != sbuf[e - 1]);
             uint32_t tot;
-            uint32_t pos = block_excl_scan(mine, red, &tot);
+            uint32_t pos = block_excl_scan<QW>(mine, red, &tot);
             for (int e = e0; e < e1; ++e)
                 if (e == 0 || sbuf[e] != sbuf[e - 1])
                     cand[pos++] = (uint32_t)sbuf[e];
@@ -475,15 +547,15 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
         }
         __syncthreads();
         const uint32_t uc = s_ucount;
-        // score: a wave takes NR candidates c, c + kQWaves, ... together
+        // score: a wave takes NR candidates c, c + QW, ... together
         // (their loads overlap); those past the end repeat c
         auto score_all = [&](auto nr_tag, auto scorer) {
             constexpr int NR = decltype(nr_tag)::value;
-            for (uint32_t c = wid; c < uc; c += NR * kQWaves) {
+            for (uint32_t c = wid; c < uc; c += NR * QW) {
                 int64_t row[NR];
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
-                    row[r] = cand[c + r * kQWaves < uc ? c + r * kQWaves : c];
+                    row[r] = cand[c + r * QW < uc ? c + r * QW : c];
                 float acc[NR], xx[NR];
                 scorer(row, acc, xx);
 #pragma unroll
@@ -497,8 +569,8 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
                         const float cs = (qn > 0.0f && xn > 0.0f) ? ac / (qn * xn) : 0.0f;
                         sc = 1.0f - cs;
                     }
-                    if (lane == 0 && c + r * kQWaves < uc)
-                        sbuf[c + r * kQWaves] =
+                    if (lane == 0 && c + r * QW < uc)
+                        sbuf[c + r * QW] =
                             ((uint64_t)__float_as_uint(fmaxf(sc, 0.0f)) << 32) | (uint64_t)row[r];
                 }
             }
@@ -528,14 +600,14 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
         int m2 = 1;
         while (m2 < tot)
             m2 <<= 1;
-        for (int e = tid; e < m2; e += kQThreads) {
+        for (int e = tid; e < m2; e += QT) {
             if (e >= (int)uc)
                 sbuf[e] = e < tot ? topk[e - uc] : ~0ull;
         }
         __syncthreads();
-        block_bitonic(sbuf, m2);
+        sort_keys(sbuf, m2);
         int nk = tot < a.k ? tot : a.k;
-        for (int e = tid; e < nk; e += kQThreads)
+        for (int e = tid; e < nk; e += QT)
             topk[e] = sbuf[e];
         __syncthreads();
         if (tid == 0)
@@ -544,7 +616,7 @@ __global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     }
 
     const int kc = s_kcur;
-    for (int r = tid; r < a.k; r += kQThreads) {
+    for (int r = tid; r < a.k; r += QT) {
         int64_t id = -1;
         float sc = INFINITY;
         if (r < kc) {
@@ -641,10 +713,16 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
     a.ncand = ncand;
     size_t lds = (size_t)((Q->d * 4 + 15) & ~15) + (size_t)(5 * kMaxLists + 1) * 4 + 16 +
                  (size_t)(kSortCap + kMaxK) * 8 + (size_t)kCap * 4;
-    LSH_HIP(hipFuncSetAttribute((const void *)query_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(query_kernel, dim3((unsigned)Q->n), dim3(kQThreads), lds,
-                       (hipStream_t)stream, a);
+    const bool solo = Q->n <= device_cu_count();
+    const void *fn = solo ? (const void *)query_kernel<kQThreadsSolo>
+                          : (const void *)query_kernel<kQThreads>;
+    LSH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (solo)
+        hipLaunchKernelGGL(query_kernel<kQThreadsSolo>, dim3((unsigned)Q->n), dim3(kQThreadsSolo),
+                           lds, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(query_kernel<kQThreads>, dim3((unsigned)Q->n), dim3(kQThreads), lds,
+                           (hipStream_t)stream, a);
     LSH_LAUNCHED("query_kernel");
     return LSH_OK;
 }
