@@ -1273,14 +1273,16 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         a.mask_off = (int32_t)mo;
         return off;
     };
-    // more waves per workgroup amortise the table; fewer fit more workgroups
+    // more waves per workgroup amortise the table and build it sooner (also
+    // for a few rows: waves without a row only help build it); fewer fit
+    // more workgroups
     int waves = 8;
-    while (waves > 1 && (lds_for(waves) > lds_max || waves > nblk))
+    while (waves > 1 && lds_for(waves) > lds_max)
         waves >>= 1;
     if (lds_for(waves) > lds_max && stage_on) {
         stage_on = false; // keys too many to stage: store them directly
         waves = 8;
-        while (waves > 1 && (lds_for(waves) > lds_max || waves > nblk))
+        while (waves > 1 && lds_for(waves) > lds_max)
             waves >>= 1;
     }
     size_t lds = lds_for(waves);
