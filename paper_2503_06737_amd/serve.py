@@ -149,14 +149,13 @@ class Server:
         ins = [r for r in batch if r.kind == "insert"]
         qs = [r for r in batch if r.kind == "query"]
         if ins:
-            pts = np.concatenate([r.points for r in ins])
-            self._insert(pinned(pts))
+            pts = pinned([r.points for r in ins])
+            self._insert(pts)
             self.stats.points_hashed += pts.shape[0]
         if qs:
-            pts = np.concatenate([r.points for r in qs])
-            Q = pinned(pts)
+            Q = pinned([r.points for r in qs])
             qk = self._hash(Q)
-            self.stats.points_hashed += pts.shape[0]
+            self.stats.points_hashed += Q.shape[0]
             lo = 0
             while lo < len(qs):     # one call per watermark group
                 hi = lo
@@ -190,8 +189,16 @@ class Server:
                 r.watermark = seen
         self.arrived_inserts = seen
 
-        def pinned(a: np.ndarray) -> torch.Tensor:
-            return torch.from_numpy(a).pin_memory().to(dev, non_blocking=True)
+        def pinned(arrs: list) -> torch.Tensor:
+            # the requests' points copied once, into one pinned buffer (the
+            # host allocator keeps it until the copy to the device is done)
+            m = sum(a.shape[0] for a in arrs)
+            host = torch.empty((m, self.d), dtype=torch.float32, pin_memory=True)
+            off = 0
+            for a in arrs:
+                host[off:off + a.shape[0]].copy_(torch.from_numpy(a))
+                off += a.shape[0]
+            return host.to(dev, non_blocking=True)
 
         inflight: deque = deque()
         live = 0      # bytes of the batches in flight
