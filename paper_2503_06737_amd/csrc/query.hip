@@ -39,6 +39,7 @@ struct QSeg {
     const uint32_t *offs;
     const int64_t *nuniq;
     int64_t n;
+    int64_t id_end; // id_base + n: every id of the segment is below it
 };
 
 struct QueryArgs {
@@ -208,18 +209,22 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *a, uint32_t 
     return lo;
 }
 
-// First index of uk[0, n) (ascending) whose key is >= key.  Probes are
+// First index of uk[0, n) (ascending) whose key is >= key; *at gets that
+// key (the search has read it) when the index is below n.  Probes are
 // placed by interpolation on the key values (the bucket keys of 64-bit
 // digests are spread evenly over the key range); after a probe that leaves
 // more than half of the range, the next one bisects, so a search takes at
 // most about twice the probes of plain bisection.
-__device__ __forceinline__ int64_t lower_bound_keys(const uint64_t *uk, int64_t n, uint64_t key)
+__device__ __forceinline__ int64_t lower_bound_keys(const uint64_t *uk, int64_t n, uint64_t key,
+                                                    uint64_t *at)
 {
     if (n == 0)
         return 0;
     uint64_t klo = uk[0], khi = uk[n - 1];
-    if (key <= klo)
+    if (key <= klo) {
+        *at = klo;
         return 0;
+    }
     if (key > khi)
         return n;
     int64_t lo = 0, hi = n - 1; // uk[lo] < key <= uk[hi]: the answer is in (lo, hi]
@@ -244,6 +249,7 @@ __device__ __forceinline__ int64_t lower_bound_keys(const uint64_t *uk, int64_t 
         }
         bisect = !bisect && 2 * (hi - lo) > len;
     }
+    *at = khi;
     return hi;
 }
 
@@ -422,15 +428,17 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(2))) void qu
         uint64_t key = a.qkeys[(int64_t)t * a.qkey_ld + q];
         const uint64_t *uk = S.ukeys + (int64_t)t * S.n;
         const int64_t nu = S.nuniq[t];
-        const int64_t lo = lower_bound_keys(uk, nu, key);
+        uint64_t kat = 0;
+        const int64_t lo = lower_bound_keys(uk, nu, key, &kat);
         uint32_t st = 0, en = 0;
-        if (lo < nu && uk[lo] == key) {
+        if (lo < nu && kat == key) {
             const uint32_t *of = S.offs + (int64_t)t * (S.n + 1);
             st = of[lo];
             en = of[lo + 1];
             // ids of a bucket ascend: drop the tail at or above the watermark
+            // (none when the whole segment lies below it)
             const uint32_t *ids = S.ids + (int64_t)t * S.n;
-            if (ids[en - 1] >= a.watermark)
+            if (S.id_end > (int64_t)a.watermark && ids[en - 1] >= a.watermark)
                 en = lower_bound_u32(ids, st, en, a.watermark);
         }
         lst_start[li] = st;
@@ -680,6 +688,7 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
         a.seg[s].offs = v.offs;
         a.seg[s].nuniq = v.nuniq;
         a.seg[s].n = v.n;
+        a.seg[s].id_end = v.id_base + v.n;
         if (v.id_base + v.n > maxid)
             maxid = v.id_base + v.n;
     }
