@@ -90,7 +90,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--quick", action="store_true", help="skip dense/SRP/query extras")
+    ap.add_argument("--quick", action="store_true", help="skip every extra")
+    ap.add_argument("--extras", default="steps,query,hcs,precision",
+                    help="comma-separated extras: steps (dense E2LSH, CS-SRP, dense SRP), "
+                         "query (latency and serving), hcs, precision")
     ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
     ap.add_argument("--no-copy", action="store_true", help="skip the streaming-copy ceiling")
     args = ap.parse_args()
@@ -204,10 +207,11 @@ def main():
     print(f"[bench] CS-E2LSH step {np.median(step_ms):.3f} ms (hash {hash_med:.3f})",
           file=sys.stderr, flush=True)
 
-    if not args.quick:
+    ex = set() if args.quick else {e for e in args.extras.split(",") if e}
+    if ex:
         extra = {}
-        for name, fam, dense in (("dense_e2lsh", 0, True), ("cs_srp", 1, False),
-                                 ("dense_srp", 1, True)):
+        other_steps = (("dense_e2lsh", 0, True), ("cs_srp", 1, False), ("dense_srp", 1, True))
+        for name, fam, dense in (other_steps if "steps" in ex else ()):
             for _ in range(2):
                 step(fam, dense)
             torch.cuda.synchronize()
@@ -223,9 +227,11 @@ def main():
                 e["hash_gbs"] = round(n * bytes_per_point / (hs_ms * 1e-3) / 1e9, 1)
             extra[name] = e
             print(f"[bench] {name}: {e}", file=sys.stderr, flush=True)
-        extra["speedup_cs_vs_dense_e2lsh"] = {
-            "hash_only": round(extra["dense_e2lsh"]["hash_ms"] / hash_med, 2),
-            "hash_plus_index": round(extra["dense_e2lsh"]["ms_per_step"] / float(np.median(step_ms)), 2)}
+        if "steps" in ex:
+            extra["speedup_cs_vs_dense_e2lsh"] = {
+                "hash_only": round(extra["dense_e2lsh"]["hash_ms"] / hash_med, 2),
+                "hash_plus_index": round(extra["dense_e2lsh"]["ms_per_step"] /
+                                         float(np.median(step_ms)), 2)}
 
         # query latency: hash + probe + exact re-rank of query batches against a
         # CS-E2LSH index of the serving-shaped workload (2M x 960 Gaussian
@@ -235,12 +241,15 @@ def main():
         del X, keys, mem, ws
         index_holder.clear()
         torch.cuda.empty_cache()
-        extra["query_latency"], extra["serving"] = query_latency(torch, lsh, synth, dev)
-        torch.cuda.empty_cache()
-        extra["hcs_vs_cs"] = hcs_throughput(torch, lsh, dev)
-        torch.cuda.empty_cache()
-        extra["precision"] = precision_path(torch, lsh, dev)
-        torch.cuda.empty_cache()
+        if "query" in ex:
+            extra["query_latency"], extra["serving"] = query_latency(torch, lsh, synth, dev)
+            torch.cuda.empty_cache()
+        if "hcs" in ex:
+            extra["hcs_vs_cs"] = hcs_throughput(torch, lsh, dev)
+            torch.cuda.empty_cache()
+        if "precision" in ex:
+            extra["precision"] = precision_path(torch, lsh, dev)
+            torch.cuda.empty_cache()
         res["extras"] = extra
 
     # ---------------------------------------------------------------- CPU oracle
