@@ -235,6 +235,21 @@ __device__ __forceinline__ void block_or_and(const uint64_t *keys, int64_t cnt, 
     __syncthreads();
 }
 
+// h[d] += 1 for every active lane: one add of the lane count when all
+// active lanes hold the same digit (tables with few distinct keys would
+// otherwise queue 64 adds on one LDS address), else one add per lane.
+__device__ __forceinline__ void hist_add(uint32_t *h, uint32_t d)
+{
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+    const uint64_t act = __ballot(1);
+    if (__ballot(d == d0) == act) {
+        if (lane_id() == __builtin_ctzll(act))
+            atomicAdd(&h[d0], (uint32_t)__popcll(act));
+    } else {
+        atomicAdd(&h[d], 1u);
+    }
+}
+
 // OR / AND of every key of a table and, guessing that the table's top key
 // bit varies (true of 64-bit digests), the tile's counts of the segment
 // digit key >> (64 - B).  msd_up recounts the tables where the
@@ -270,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void mask_up_kernel(BuildArgs a)
     for (int it = 0; it < kItems; ++it) {
         const int64_t i = base + it * kThreads + threadIdx.x;
         if (full || i < a.n)
-            atomicAdd(&h[(uint32_t)(v[it] >> shift)], 1u);
+            hist_add(h, (uint32_t)(v[it] >> shift));
     }
     vo = wave_or64(vo);
     va = wave_and64(va);
@@ -323,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void msd_up_kernel(BuildArgs a)
     for (int it = 0; it < kItems; ++it) {
         const int64_t i = base + it * kThreads + threadIdx.x;
         if (i < a.n)
-            atomicAdd(&h[(uint32_t)(v[it] >> shift) & (uint32_t)(R - 1)], 1u);
+            hist_add(h, (uint32_t)(v[it] >> shift) & (uint32_t)(R - 1));
     }
     __syncthreads();
     uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
