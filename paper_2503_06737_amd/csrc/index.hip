@@ -98,6 +98,30 @@ __device__ __forceinline__ int top_shift(uint64_t vm, int bits)
     return hb >= bits ? hb - bits + 1 : 0;
 }
 
+// The segment digit of a table whose varying key bits (OR & ~AND over its
+// keys) number 1..B: those bits, compacted in order (bit i of the digit is
+// the i-th lowest varying bit).  The digit then orders the keys exactly as
+// the keys do (they agree on every other bit) and separates all distinct
+// keys, so each segment is one run of equal keys.  cmask is uniform.
+__device__ __forceinline__ uint32_t compact_bits(uint64_t k, uint64_t cmask)
+{
+    uint32_t d = 0;
+    for (int i = 0; cmask; ++i) {
+        const int b = __builtin_ctzll(cmask);
+        d |= (uint32_t)((k >> b) & 1u) << i;
+        cmask &= cmask - 1;
+    }
+    return d;
+}
+
+// The varying bits of table t when they take the compacted digit (1..B of
+// them), else 0 (the digit is then the top B bits from the highest varying one).
+__device__ __forceinline__ uint64_t compact_mask(uint64_t tor, uint64_t tand, int bits)
+{
+    const uint64_t vm = tor & ~tand;
+    return vm && __popcll(vm) <= bits ? vm : 0ull;
+}
+
 __device__ __forceinline__ bool chunk_varies(uint64_t vm, int p)
 {
     return ((vm >> (8 * p)) & 255u) != 0;
@@ -312,7 +336,8 @@ __global__ __launch_bounds__(kThreads) void mask_up_kernel(BuildArgs a)
 
 __device__ __forceinline__ bool guess_holds(const BuildArgs &a, int t)
 {
-    return top_shift(a.tor[t] & ~a.tand[t], a.msd_bits) == 64 - a.msd_bits;
+    return !compact_mask(a.tor[t], a.tand[t], a.msd_bits) &&
+           top_shift(a.tor[t] & ~a.tand[t], a.msd_bits) == 64 - a.msd_bits;
 }
 
 // Tables whose top key bit does not vary: count the segment digit (the top
@@ -328,6 +353,7 @@ __global__ __launch_bounds__(kThreads) void msd_up_kernel(BuildArgs a)
         h[i] = 0;
     __syncthreads();
     const int shift = top_shift(a.tor[t] & ~a.tand[t], a.msd_bits);
+    const uint64_t cmask = compact_mask(a.tor[t], a.tand[t], a.msd_bits);
     const uint64_t *k = a.kin + (int64_t)t * a.key_ld;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     uint64_t v[kItems];
@@ -338,7 +364,8 @@ __global__ __launch_bounds__(kThreads) void msd_up_kernel(BuildArgs a)
     for (int it = 0; it < kItems; ++it) {
         const int64_t i = base + it * kThreads + threadIdx.x;
         if (i < a.n)
-            hist_add(h, (uint32_t)(v[it] >> shift) & (uint32_t)(R - 1));
+            hist_add(h, cmask ? compact_bits(v[it], cmask)
+                              : (uint32_t)(v[it] >> shift) & (uint32_t)(R - 1));
     }
     __syncthreads();
     uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
@@ -516,7 +543,8 @@ template <int RMAX, int IT = kItems, int RLOG = __builtin_ctz(RMAX)>
 __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX, IT> &s, const uint64_t *kin,
                                              const uint32_t *iin, uint32_t id0, int cnt,
                                              int shift, int bits, const uint32_t *goff,
-                                             uint64_t *kout, uint32_t *iout)
+                                             uint64_t *kout, uint32_t *iout,
+                                             uint64_t cmask = 0)
 {
     const int R = 1 << bits;
     const uint32_t dmask = (uint32_t)R - 1u;
@@ -535,7 +563,14 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX, IT> &s, const uint
     // digit of 64-bit digests) only that half is read.
     uint32_t dg[IT];
     const uint32_t *kw = (const uint32_t *)kin;
-    if (shift >= 32 || shift + bits <= 32) {
+    if (cmask) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int i = wbase + it * kWave + lane;
+            const uint64_t k = kin[min(i, cnt - 1)];
+            dg[it] = compact_bits(k, cmask) | (i < cnt ? 0u : dmask);
+        }
+    } else if (shift >= 32 || shift + bits <= 32) {
         const int h = shift >= 32 ? 1 : 0, sh = shift - 32 * h;
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -624,7 +659,8 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<RMAX, IT> &s, const uint
         for (int u = 0; u < IT; ++u) {
             const int q = u * kThreads + tid;
             if (q < cnt) {
-                const uint32_t d = (uint32_t)(kv[u] >> shift) & dmask;
+                const uint32_t d = cmask ? compact_bits(kv[u], cmask)
+                                         : (uint32_t)(kv[u] >> shift) & dmask;
                 const uint32_t g = s.goff[d] + ((uint32_t)q - s.lbase[d]);
                 kout[g] = kv[u];
                 iout[g] = iv[u];
@@ -649,6 +685,7 @@ msd_scatter_kernel(BuildArgs a)
     const int t = blockIdx.y;
     const int R = 1 << a.msd_bits;
     const int shift = top_shift(a.tor[t] & ~a.tand[t], a.msd_bits);
+    const uint64_t cmask = compact_mask(a.tor[t], a.tand[t], a.msd_bits);
     // kMsdTile / kTile counted tiles at once: their run of a digit starts
     // where the first tile's run starts and covers the others
     const int64_t base = (int64_t)blockIdx.x * kMsdTile;
@@ -662,13 +699,13 @@ msd_scatter_kernel(BuildArgs a)
     const uint32_t id0 = a.id_base + (uint32_t)base;
     if (a.msd_bits <= 8)
         scatter_tile<kMsdRadixMax, kMsdItems, 8>(s, kin, nullptr, id0, cnt, shift, a.msd_bits,
-                                                 goff, ko, io);
+                                                 goff, ko, io, cmask);
     else if (a.msd_bits == 9)
         scatter_tile<kMsdRadixMax, kMsdItems, 9>(s, kin, nullptr, id0, cnt, shift, a.msd_bits,
-                                                 goff, ko, io);
+                                                 goff, ko, io, cmask);
     else
         scatter_tile<kMsdRadixMax, kMsdItems, 10>(s, kin, nullptr, id0, cnt, shift, a.msd_bits,
-                                                  goff, ko, io);
+                                                  goff, ko, io, cmask);
 }
 
 // ------------------------------------------------- segment sort in LDS

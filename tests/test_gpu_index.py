@@ -96,6 +96,27 @@ def test_segment_digit_widths_8_and_9(n):
     _check(keys)
 
 
+@pytest.mark.parametrize("nvary", [1, 8, 9])
+def test_scattered_varying_bits(nvary):
+    """Keys that differ only in nvary bits spread over the word (n = 300k:
+    8-bit segment digits).  Up to 8 varying bits form the compacted digit
+    (every segment one run of equal keys); 9 take the top-bits digit, whose
+    segments then hold several keys (low varying bits outside the window)."""
+    n, L = 300_000, 3
+    g = _rng(70 + nvary)
+    pos = np.sort(g.choice(64, nvary, replace=False))
+    base = np.uint64(g.integers(0, 2**63)) & ~np.uint64(sum(1 << int(p) for p in pos))
+    bits = g.integers(0, 2, (L, n, nvary), dtype=np.uint64)
+    # skew: half of the points share one pattern (a heavy bucket)
+    bits[:, : n // 2] = bits[:, :1]
+    keys = np.full((L, n), base, np.uint64)
+    for i, p in enumerate(pos):
+        keys |= bits[:, :, i] << np.uint64(int(p))
+    for t in range(L):
+        g.shuffle(keys[t])
+    _check(keys)
+
+
 def test_empty_index():
     dev()
     import torch
