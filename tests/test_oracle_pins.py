@@ -251,6 +251,36 @@ def test_discretise_hand_cases(orc):
     assert bits.tolist() == g["srp_bits"]
 
 
+def test_srp_near_edge_band_uses_row_norm(orc):
+    """The SRP near-edge band is |y| < 1e-6 * ||x||_2, with ||x||_2 of the row
+    being hashed (worked cases: rows (3, 4, t), band 5e-6).  A band built from
+    ||x||^2, max|x| or ||x||_1 fails one of the rows."""
+    g = _gold("srp_near_edge_cases.json")
+    x = np.array(g["x"])
+    out = orc.hash_points(x, orc.SRP, 1, g["m"], kind="cs", h=np.array(g["h"]),
+                          s=np.array(g["s"]))
+    assert out["codes"].tolist() == g["bits"]
+    assert out["near"].tolist() == g["near"]
+    # the same band through disc_srp with the norms passed explicitly
+    bits, near = orc.disc_srp(x, np.full(len(x), 5.0))
+    assert near.tolist() == g["near"] and bits.tolist() == g["bits"]
+
+
+def test_row_norms_pythagorean(orc):
+    g = _gold("row_norm_cases.json")
+    assert orc.row_norms(np.array(g["rows"])).tolist() == g["norms"]
+
+
+def test_e2lsh_codes_saturate_to_int32(orc):
+    """floor(v / w) outside the int32 range saturates to its nearest end; the
+    largest and smallest representable codes are kept exactly."""
+    g = _gold("e2lsh_int32_saturation.json")
+    for row in g["rows"]:
+        y = np.array([row["y"]])
+        codes, _ = orc.disc_e2lsh(y, np.zeros(y.shape[1], np.float32), row["w"], row["alpha"])
+        assert codes[0].tolist() == row["codes"]
+
+
 def test_hash_points_cs_e2lsh_uses_sqrt_m(orc):
     """CS-E2LSH scales the sketch by sqrt(m) before the shift (Definition CS_Eucl_LSH)."""
     g = np.random.default_rng(22)
