@@ -68,6 +68,14 @@ struct QueryArgs {
     int32_t *ncand;
 };
 
+// OCP E4M3FN -> FP32 by the gfx950 conversion instruction: exact for every
+// finite pattern (subnormals included), and the NaN patterns S.1111.111 give
+// NaN, as the stored value defines.
+__device__ __forceinline__ float fp8_value(uint32_t b)
+{
+    return __builtin_amdgcn_cvt_f32_fp8((int)b, 0);
+}
+
 __device__ __forceinline__ float load_val(const void *x, int dt, const float *scale, int64_t row,
                                           int64_t ld, int32_t j)
 {
@@ -76,9 +84,7 @@ __device__ __forceinline__ float load_val(const void *x, int dt, const float *sc
         return ((const float *)x)[row * ld + j];
     if (dt == LSH_BF16)
         return sc * __uint_as_float((uint32_t)((const uint16_t *)x)[row * ld + j] << 16);
-    uint32_t b = ((const uint8_t *)x)[row * ld + j];
-    float mag = __uint_as_float((b & 0x7fu) << 20) * 0x1.0p120f;
-    return sc * __uint_as_float(__float_as_uint(mag) | ((b & 0x80u) << 24));
+    return sc * fp8_value(((const uint8_t *)x)[row * ld + j]);
 }
 
 // Element off of a row of type DT (sc: the row's scale; 1 for FP32).
@@ -89,9 +95,7 @@ __device__ __forceinline__ float load_dt(const void *x, float sc, int64_t off)
         return ((const float *)x)[off];
     if constexpr (DT == LSH_BF16)
         return sc * __uint_as_float((uint32_t)((const uint16_t *)x)[off] << 16);
-    const uint32_t b = ((const uint8_t *)x)[off];
-    const float mag = __uint_as_float((b & 0x7fu) << 20) * 0x1.0p120f;
-    return sc * __uint_as_float(__float_as_uint(mag) | ((b & 0x80u) << 24));
+    return sc * fp8_value(((const uint8_t *)x)[off]);
 }
 
 // Sums over NR candidate rows by a wave (each lane a partial sum per row):

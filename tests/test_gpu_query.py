@@ -114,11 +114,13 @@ def test_query_one_bucket_is_exact_knn_with_windows():
         assert len(set(order[:60]) ^ set(to_host(got[0])[i][:60])) <= 4
 
 
-def test_query_low_precision_base():
-    """Re-rank over BF16 points with per-row scales (dequantised on the fly)."""
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_query_low_precision_base(kind):
+    """Re-rank over BF16 / FP8-E4M3FN points with per-row scales (dequantised
+    on the fly)."""
     dev()
     x = synth.gaussian_clusters(3000, 512, 10, 0.1, 41)
-    q, sc = synth.quantise_rows(x, "bf16")
+    q, sc = synth.quantise_rows(x, kind)
     x64 = oracle.decode(q, sc)
     Q = x64[:50].astype(np.float32)
     h, s = synth.cs_state(512, 64, 42)
@@ -132,4 +134,4 @@ def test_query_low_precision_base():
     rqk = oracle.hash_points(Q.astype(np.float64), 1, 8, 8, kind="cs", h=h, s=s)["keys"]
     assert (to_host(keys, np.uint64) == rk).all() and (to_host(qkeys, np.uint64) == rqk).all()
     ref = oracle.query([oracle.build_index(rk)], x64, Q.astype(np.float64), rqk, 10, 3000, 1)
-    _compare(ids, scv, nc, *ref, what="bf16 base")
+    _compare(ids, scv, nc, *ref, what=f"{kind} base")
