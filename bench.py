@@ -358,34 +358,70 @@ def _device_clusters(torch, n, d, n_centres, sigma, seed, dev):
     return x
 
 
+def table_stats(torch, idx, n):
+    """Bucket statistics of a built index: tables whose every point shares one
+    key (constant tables), distinct keys per table, the largest bucket."""
+    _, _, offs, nuniq = idx.arrays()
+    nu = nuniq.long()
+    ar = torch.arange(offs.shape[1] - 1, device=offs.device)
+    sizes = (offs[:, 1:].long() - offs[:, :-1].long()) * (ar[None, :] < nu[:, None])
+    big = sizes.max(dim=1).values.float() / max(n, 1)
+    return {"constant_tables": int((nu == 1).sum().item()),
+            "distinct_keys_median": int(nu.median().item()), "distinct_keys_min": int(nu.min().item()),
+            "largest_bucket_frac_max": round(float(big.max().item()), 4),
+            "largest_bucket_frac_median": round(float(big.median().item()), 4)}
+
+
 def hcs_throughput(torch, lsh, dev):
-    """HCS (N = 2 and 3) vs CS hashing at m = 1024 on 500k x 4096 clusters."""
+    """HCS (N = 2 and 3) vs CS at m = 1024 on 500k x 4096 clusters: hashing
+    alone (keys only) and hash + index build.  HCS assigns its sketch
+    components to tables by the workload's seeded permutation; the bucket
+    statistics are reported with and without it (contiguous tables sit inside
+    one mode slice, and an empty mode bin makes such a table constant)."""
     from paper_2503_06737_amd import synth
-    n, d, K, L, w = 500_000, 4096, 16, 64, 4.0
-    X = _device_clusters(torch, n, d, 200, 0.2, 250306737 + 3000, dev)
-    h, s = synth.cs_state(d, K * L, 7)
-    b = torch.from_numpy(synth.shifts(K * L, w, 7)).to(dev)
+    wl = synth.C3
+    n, d, K, L, w = wl.n, wl.d, wl.K, wl.L, wl.w
+    X = _device_clusters(torch, n, d, wl.n_centres, wl.sigma, wl.seed, dev)
+    h, s = wl.cs()
+    b = torch.from_numpy(wl.b()).to(dev)
+    slot = torch.from_numpy(wl.slots().view(np.int32)).to(dev)
     hd, sd = torch.from_numpy(h.view(np.int32)).to(dev), torch.from_numpy(s).to(dev)
     bytes_pp = d * 4 + 8 * L
-    res = {"n": n, "d": d, "m": K * L, "K": K, "L": L}
+    keys = torch.empty((L, n), dtype=torch.int64, device=dev)
+    mem = torch.empty(lsh.lib().lsh_index_bytes(n, L), dtype=torch.uint8, device=dev)
+    ws = torch.empty(lsh.lib().lsh_build_workspace_bytes(n, L), dtype=torch.uint8, device=dev)
+    res = {"workload": wl.name, "n": n, "d": d, "m": K * L, "K": K, "L": L}
 
-    def bench_fn(fn):
+    def bench_fn(hash_fn):
+        def step():
+            keys.copy_(hash_fn()["keys"])
+            return lsh.lsh_build_index(keys, mem=mem, ws=ws)
         for _ in range(2):
-            fn()
+            hash_fn()
+            step()
         torch.cuda.synchronize()
-        med, _ = timed(torch, fn, 5)
-        return {"ms": round(med, 4), "gbs": round(n * bytes_pp / (med * 1e-3) / 1e9, 1)}
+        med, _ = timed(torch, hash_fn, 5)
+        smed, _ = timed(torch, step, 5)
+        idx = step()
+        e = {"hash_ms": round(med, 4), "gbs": round(n * bytes_pp / (med * 1e-3) / 1e9, 1),
+             "hash_copy_index_ms": round(smed, 4), **table_stats(torch, idx, n)}
+        assert idx.check() == (0, 0)
+        return e
 
     res["cs"] = bench_fn(lambda: lsh.lsh_hash_cs(X, hd, sd, family=0, K=K, L=L, w=w, b=b))
-    for name, dk, mk in (("hcs_n2", (64, 64), (32, 32)), ("hcs_n3", (16, 16, 16), (8, 8, 16))):
-        hk, sk = synth.hcs_state(dk, mk, 7)
+    for i, name in enumerate(("hcs_n2", "hcs_n3")):
+        dk, mk = wl.hcs[i]
+        hk, sk = wl.hcs_state(i)
         hkd = torch.from_numpy(np.concatenate(hk).view(np.int32)).to(dev)
         skd = torch.from_numpy(np.concatenate(sk)).to(dev)
         res[name] = bench_fn(lambda: lsh.lsh_hash_hcs(X, dk, mk, hkd, skd, family=0, K=K, L=L,
-                                                      w=w, b=b))
+                                                      w=w, b=b, comp_slot=slot))
         res[name]["dk"], res[name]["mk"] = list(dk), list(mk)
+        keys.copy_(lsh.lsh_hash_hcs(X, dk, mk, hkd, skd, family=0, K=K, L=L, w=w, b=b)["keys"])
+        res[name]["contiguous_tables"] = table_stats(torch, lsh.lsh_build_index(keys, mem=mem,
+                                                                                ws=ws), n)
     print(f"[bench] hcs_vs_cs {res}", file=sys.stderr, flush=True)
-    del X
+    del X, keys, mem, ws
     return res
 
 

@@ -27,11 +27,13 @@
  *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
  *     default stream).  Nothing blocks except argument validation on the host.
  *   - Return value: LSH_OK, or a negative lsh_status with a message available
- *     from lsh_last_error() (thread-local).  On error nothing was enqueued.
+ *     from lsh_last_error() (thread-local).  On LSH_EINVAL, LSH_ENOMEM and
+ *     LSH_ERANGE nothing was enqueued.  LSH_EHIP means the runtime refused a
+ *     launch or copy; kernels of the same call enqueued before it may run.
  *   - n = 0 is a valid no-op wherever n appears.
  *   - Hashcode length m = K * L: one sketch of m components per point, split
- *     into L tables of K consecutive components (table t owns components
- *     [tK, tK+K)).
+ *     into L tables of K components.  By default table t owns components
+ *     [tK, tK+K); lsh_disc.comp_slot assigns them to tables in another order.
  */
 #ifndef LSH_H
 #define LSH_H
@@ -80,12 +82,28 @@ typedef struct lsh_disc {
     int32_t L;        /* number of tables, >= 1 */
     float w;          /* E2LSH bucket width, w > 0 (ignored for SRP) */
     const float *b;   /* [m] shifts in [0, w) (E2LSH only; NULL for SRP) */
-    int32_t recheck;  /* 0: FP32 result as computed.  1: every component whose
-                         FP32 value lies within a rigorous bound of its
-                         rounding error from a bin edge (E2LSH) or from zero
-                         (SRP) is recomputed in FP64 in ascending coordinate
-                         order, so codes equal those of an FP64 evaluation.
-                         CS/HCS only; needs d <= 32768. */
+    int32_t recheck;  /* 0: the sketch is summed exactly in fixed point (each
+                         term truncated to a multiple of 2^-k, k chosen per row
+                         so no bin can overflow) and discretised in FP32.  Such
+                         a code differs from the FP64 evaluation only when v/w
+                         lies within sqrt(m) * scale * (c_max + 1) * 2^-k / w +
+                         2^-22 * |v/w| of an integer (c_max: the largest bin
+                         population); at |v/w| < 128 and unit-scale rows this
+                         is far below 1e-4 (tiny w or huge values can exceed
+                         it: use recheck).  1: every component whose value lies
+                         within a rigorous bound of its error from a bin edge
+                         (E2LSH) or from zero (SRP) is recomputed in FP64 in
+                         ascending coordinate order, so codes equal those of an
+                         FP64 evaluation.  CS/HCS only; needs d <= 32768. */
+    const uint32_t *comp_slot; /* [m] device array or NULL (CS/HCS only).  Sketch
+                         component l is written to code position comp_slot[l],
+                         i.e. component comp_slot[l] % K of table
+                         comp_slot[l] / K.  Meant to be a permutation of
+                         [0, m) (a position assigned several components holds
+                         their sum).  NULL: component l is position l, so table
+                         t owns components [tK, tK+K).  A permutation drawn at
+                         random spreads the components that share a mode index
+                         of a higher-order sketch over all tables. */
 } lsh_disc;
 
 /* Outputs.  Any pointer may be NULL to skip that output. */
@@ -101,7 +119,10 @@ typedef struct lsh_out {
                            [0] components recomputed in FP64 (recheck = 1),
                            [1] of those, components whose code changed,
                            [2] E2LSH codes that saturated to the int32 range,
-                           [3] reserved, left unchanged */
+                           [3] coordinates whose hash state is out of range
+                               (h[j] >= m, a per-mode h_k >= m_k, or
+                               comp_slot >= m); such an entry is taken as 0.
+                               Zero for valid state. */
 } lsh_out;
 
 /*
@@ -142,7 +163,8 @@ lsh_status lsh_hash_hcs(const lsh_points *pts, int32_t N, const int32_t *d_k, co
 
 /* Dense E2LSH / SRP (Section 3.1): y = x R on FP32 matrix cores, then
  * floor((y + b)/w) (no sqrt(m) scale) or sgn(y).  R: [d][m] row-major FP32.
- * F32 points only; recheck must be 0. */
+ * F32 points only; recheck must be 0 and comp_slot NULL (permute the
+ * columns of R instead). */
 lsh_status lsh_hash_dense(const lsh_points *pts, const float *R, const lsh_disc *disc,
                           const lsh_out *out, void *stream);
 

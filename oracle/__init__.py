@@ -51,6 +51,7 @@ def _declare(L):
     L.orc_disc_e2lsh.argtypes = [vp, i64, i32, vp, f32, f64, vp, vp]
     L.orc_disc_srp.argtypes = [vp, vp, i64, i32, vp, vp]
     L.orc_row_norms.argtypes = [vp, i64, i32, vp]
+    L.orc_assign_components.argtypes = [vp, i64, i32, vp, vp]
     L.orc_keys_e2lsh.argtypes = [vp, i64, i32, i32, i32, vp]
     L.orc_keys_srp.argtypes = [vp, i64, i32, i32, i32, vp]
     L.orc_mix64.argtypes = [C.c_uint64]
@@ -133,6 +134,17 @@ def dense_proj(x: np.ndarray, R: np.ndarray) -> np.ndarray:
     return y
 
 
+def assign_components(y: np.ndarray, slot: np.ndarray) -> np.ndarray:
+    """Code position slot[l] receives sketch component l (a permutation of range(m))."""
+    y = np.ascontiguousarray(y, np.float64)
+    n, m = y.shape
+    slot = np.ascontiguousarray(slot, np.uint32)
+    assert slot.shape == (m,) and (slot < m).all()
+    out = np.empty((n, m), np.float64)
+    lib().orc_assign_components(_p(y), n, m, _p(slot), _p(out))
+    return out
+
+
 def row_norms(x: np.ndarray) -> np.ndarray:
     x = np.ascontiguousarray(x, np.float64)
     out = np.empty(x.shape[0], np.float64)
@@ -192,11 +204,12 @@ def keys_srp(bits: np.ndarray, K: int, L: int) -> np.ndarray:
 
 def hash_points(x: np.ndarray, family: int, K: int, L: int, *, kind: str, w: float = 1.0,
                 b: np.ndarray | None = None, h=None, s=None, m: int | None = None, dk=None,
-                mk=None, hk=None, sk=None, R=None) -> dict:
-    """Project (kind in {"cs", "hcs", "dense"}), discretise and key FP64 points x.
+                mk=None, hk=None, sk=None, R=None, comp_slot=None) -> dict:
+    """Project (kind in {"cs", "hcs", "dense"}), assign the components to code
+    positions (comp_slot, identity when None), discretise and key FP64 points x.
 
-    Returns y (projection before scaling), codes (E2LSH codes or SRP bits),
-    near (near-edge flags), keys [L][n].
+    Returns y (projection before scaling, in code-position order), codes
+    (E2LSH codes or SRP bits), near (near-edge flags), keys [L][n].
     """
     x = np.ascontiguousarray(x, np.float64)
     if kind == "cs":
@@ -207,6 +220,8 @@ def hash_points(x: np.ndarray, family: int, K: int, L: int, *, kind: str, w: flo
         y = dense_proj(x, R)
     else:
         raise ValueError(kind)
+    if comp_slot is not None:
+        y = assign_components(y, comp_slot)
     m = y.shape[1]
     if family == E2LSH:
         alpha = 1.0 if kind == "dense" else math.sqrt(m)

@@ -171,6 +171,23 @@ void orc_dense_proj(const double *x, int64_t n, int32_t d, const float *R, int32
     }
 }
 
+/* Assignment of sketch components to tables (a reading: the paper leaves
+ * open which of the m components form each of the tables).  Component l goes
+ * to code position slot[l] (table slot[l] / K, rank slot[l] % K); position p
+ * holds the sum of the components assigned to it, which for a permutation is
+ * the component slot^-1(p) itself. */
+void orc_assign_components(const double *y, int64_t n, int32_t m, const uint32_t *slot, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double *oi = out + i * (int64_t)m;
+        for (int32_t p = 0; p < m; ++p)
+            oi[p] = 0.0;
+        for (int32_t l = 0; l < m; ++l)
+            oi[slot[l]] += y[i * (int64_t)m + l];
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* 3. discretisation                                                         */
 /* ------------------------------------------------------------------------ */

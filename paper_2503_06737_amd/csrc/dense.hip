@@ -238,6 +238,9 @@ extern "C" lsh_status lsh_hash_dense(const lsh_points *pts, const float *R, cons
         LSH_FAIL(LSH_EINVAL, "dense projection takes FP32 points");
     if (disc->recheck)
         LSH_FAIL(LSH_EINVAL, "recheck is not available for the dense projection");
+    if (disc->comp_slot)
+        LSH_FAIL(LSH_EINVAL, "comp_slot is not available for the dense projection "
+                             "(permute the columns of R instead)");
     if (!R)
         LSH_FAIL(LSH_EINVAL, "R is NULL");
     if (!out)

@@ -85,6 +85,8 @@ struct HashArgs {
     int32_t dk[kMaxModes], mk[kMaxModes], mode_off[kMaxModes];
     const uint32_t *hk;
     const int8_t *sk;
+    // code position of each sketch component (NULL: component l is position l)
+    const uint32_t *comp_slot;
     // recheck support (workspace)
     const uint32_t *csr_off;
     const uint32_t *csr_idx;
@@ -122,8 +124,11 @@ __device__ __forceinline__ void emit_key(const HashArgs &a, int t, int64_t row, 
         a.keys[(int64_t)t * a.key_ld + row] = key;
 }
 
-// Bin of coordinate j in the sketch and its sign (neg = sign < 0).
-__device__ __forceinline__ uint32_t table_bin(const HashArgs &a, int32_t j, bool &bad,
+// Code position of coordinate j and its sign (neg = sign < 0): the sketch
+// component the coordinate adds into, then that component's position in the
+// code vector (table = position / K).  Entries out of range are taken as 0
+// and counted in `bad`.
+__device__ __forceinline__ uint32_t table_bin(const HashArgs &a, int32_t j, uint32_t &bad,
                                               uint32_t &neg_out)
 {
     uint32_t bin;
@@ -142,7 +147,7 @@ __device__ __forceinline__ uint32_t table_bin(const HashArgs &a, int32_t j, bool
             rest /= a.dk[k];
             uint32_t hb = a.hk[a.mode_off[k] + ik];
             if (hb >= (uint32_t)a.mk[k]) {
-                bad = true;
+                ++bad;
                 hb = 0;
             }
             bin += hb * stride;
@@ -151,8 +156,15 @@ __device__ __forceinline__ uint32_t table_bin(const HashArgs &a, int32_t j, bool
         }
     }
     if (bin >= (uint32_t)a.m) {
-        bad = true;
+        ++bad;
         bin = 0;
+    }
+    if (a.comp_slot) {
+        bin = a.comp_slot[bin];
+        if (bin >= (uint32_t)a.m) {
+            ++bad;
+            bin = 0;
+        }
     }
     neg_out = neg;
     return bin;
@@ -161,7 +173,7 @@ __device__ __forceinline__ uint32_t table_bin(const HashArgs &a, int32_t j, bool
 // LDS table entry of coordinate j: byte offset of its bin's slot inside a
 // wave's region, sign in bit 31.  A lane forms the LDS address of the slot
 // with one v_and_or (offset bits | its wave's region base).
-__device__ __forceinline__ uint32_t table_entry(const HashArgs &a, int32_t j, bool &bad)
+__device__ __forceinline__ uint32_t table_entry(const HashArgs &a, int32_t j, uint32_t &bad)
 {
     uint32_t neg;
     uint32_t bin = table_bin(a, j, bad, neg);
@@ -633,7 +645,7 @@ void hash_kernel(HashArgs a)
     for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4)
         *(int4 *)(w.bins + l) = make_int4(0, 0, 0, 0);
     __syncthreads();
-    bool bad = false;
+    uint32_t bad = 0;
     uint32_t *tabw = (uint32_t *)(lds + a.tab_off);
     for (int32_t j = tid; j < a.tab_entries; j += blockDim.x) {
         uint32_t ent;
@@ -661,8 +673,12 @@ void hash_kernel(HashArgs a)
     if (wid == 0)
         for (int32_t l = lane * 4; l < a.mpad; l += kWave * 4)
             *(int4 *)(w.bins + l) = make_int4(0, 0, 0, 0);
-    if (bad && a.counters && tid == 0)
-        atomicAdd(&a.counters[3], 1ull);
+    // invalid hash-state entries, counted once (every workgroup sees the same)
+    if (blockIdx.x == 0 && a.counters) {
+        const uint32_t nb = wave_sum(bad);
+        if (lane == 0 && nb)
+            atomicAdd(&a.counters[3], (unsigned long long)nb);
+    }
     __syncthreads();
     (void)nwv;
 
@@ -967,7 +983,7 @@ __global__ __launch_bounds__(1024) void csr_kernel(HashArgs a, uint32_t *off, ui
     extern __shared__ uint32_t skeys[];
     __shared__ uint32_t smax;
     const int tid = threadIdx.x;
-    bool bad = false;
+    uint32_t bad = 0; // counted by the hash kernel
     if (tid == 0)
         smax = 0;
     for (int i = tid; i < p2; i += blockDim.x)
@@ -1041,8 +1057,11 @@ WsLayout ws_layout(int32_t d, int32_t m)
 
 int esize(int dt) { return dt == LSH_F32 ? 4 : (dt == LSH_BF16 ? 2 : 1); }
 
+// dry: set the kernel up and size its grid without launching it, so that a
+// failure is reported before any kernel of the call is enqueued.
 template <int FAM, int DT, bool AL, bool RC, int CH, bool LONG = false>
-hipError_t launch_one(const HashArgs &a, int block, size_t lds, hipStream_t st, int64_t nblk)
+hipError_t launch_one(const HashArgs &a, int block, size_t lds, hipStream_t st, int64_t nblk,
+                      bool dry)
 {
     auto k = hash_kernel<FAM, DT, AL, RC, CH, LONG>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1058,6 +1077,8 @@ hipError_t launch_one(const HashArgs &a, int block, size_t lds, hipStream_t st, 
     int64_t want = nblk; // one block of RB rows per workgroup step
     int64_t cap = (int64_t)device_cu_count() * per_cu;
     int grid = (int)(want < cap ? want : cap);
+    if (dry)
+        return hipSuccess;
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, st, a);
     return hipGetLastError();
 }
@@ -1069,46 +1090,47 @@ hipError_t launch_one(const HashArgs &a, int block, size_t lds, hipStream_t st, 
 template <int DT, bool AL> constexpr int long_ch() { return AL ? 16 / Elem<DT>::per16 : 8; }
 
 template <int FAM, int DT, bool AL, bool RC>
-hipError_t launch_ch(const HashArgs &a, int ch, int block, size_t lds, hipStream_t st, int64_t nblk)
+hipError_t launch_ch(const HashArgs &a, int ch, int block, size_t lds, hipStream_t st, int64_t nblk,
+                     bool dry)
 {
     if (a.pieces > 1)
-        return launch_one<FAM, DT, AL, RC, long_ch<DT, AL>(), true>(a, block, lds, st, nblk);
+        return launch_one<FAM, DT, AL, RC, long_ch<DT, AL>(), true>(a, block, lds, st, nblk, dry);
     if constexpr (AL) {
         switch (ch) {
         case 1:
-            return launch_one<FAM, DT, AL, RC, 1>(a, block, lds, st, nblk);
+            return launch_one<FAM, DT, AL, RC, 1>(a, block, lds, st, nblk, dry);
         case 2:
-            return launch_one<FAM, DT, AL, RC, 2>(a, block, lds, st, nblk);
+            return launch_one<FAM, DT, AL, RC, 2>(a, block, lds, st, nblk, dry);
         default:
-            return launch_one<FAM, DT, AL, RC, 4>(a, block, lds, st, nblk);
+            return launch_one<FAM, DT, AL, RC, 4>(a, block, lds, st, nblk, dry);
         }
     } else {
-        return launch_one<FAM, DT, AL, RC, 8>(a, block, lds, st, nblk);
+        return launch_one<FAM, DT, AL, RC, 8>(a, block, lds, st, nblk, dry);
     }
 }
 
 template <int FAM, int DT>
 hipError_t launch_dt(const HashArgs &a, bool al, bool rc, int ch, int block, size_t lds,
-                     hipStream_t st, int64_t nblk)
+                     hipStream_t st, int64_t nblk, bool dry)
 {
     if (al)
-        return rc ? launch_ch<FAM, DT, true, true>(a, ch, block, lds, st, nblk)
-                  : launch_ch<FAM, DT, true, false>(a, ch, block, lds, st, nblk);
-    return rc ? launch_ch<FAM, DT, false, true>(a, ch, block, lds, st, nblk)
-              : launch_ch<FAM, DT, false, false>(a, ch, block, lds, st, nblk);
+        return rc ? launch_ch<FAM, DT, true, true>(a, ch, block, lds, st, nblk, dry)
+                  : launch_ch<FAM, DT, true, false>(a, ch, block, lds, st, nblk, dry);
+    return rc ? launch_ch<FAM, DT, false, true>(a, ch, block, lds, st, nblk, dry)
+              : launch_ch<FAM, DT, false, false>(a, ch, block, lds, st, nblk, dry);
 }
 
 template <int FAM>
 hipError_t launch_fam(const HashArgs &a, int dt, bool al, bool rc, int ch, int block, size_t lds,
-                      hipStream_t st, int64_t nblk)
+                      hipStream_t st, int64_t nblk, bool dry)
 {
     switch (dt) {
     case LSH_F32:
-        return launch_dt<FAM, LSH_F32>(a, al, rc, ch, block, lds, st, nblk);
+        return launch_dt<FAM, LSH_F32>(a, al, rc, ch, block, lds, st, nblk, dry);
     case LSH_BF16:
-        return launch_dt<FAM, LSH_BF16>(a, al, rc, ch, block, lds, st, nblk);
+        return launch_dt<FAM, LSH_BF16>(a, al, rc, ch, block, lds, st, nblk, dry);
     default:
-        return launch_dt<FAM, LSH_FP8_E4M3FN>(a, al, rc, ch, block, lds, st, nblk);
+        return launch_dt<FAM, LSH_FP8_E4M3FN>(a, al, rc, ch, block, lds, st, nblk, dry);
     }
 }
 
@@ -1194,6 +1216,7 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
     a.inv_w64 = 1.0 / a.w64;
     a.w_pow2 = is_pow2(a.w32);
     a.b = disc->b;
+    a.comp_slot = disc->comp_slot;
     a.keys = out->keys;
     a.key_ld = key_ld;
     a.codes = out->codes;
@@ -1292,6 +1315,14 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
     a.waves = waves;
 
     hipStream_t s = (hipStream_t)stream;
+    auto launch_hash = [&](bool dry) {
+        return disc->family == LSH_E2LSH
+                   ? launch_fam<LSH_E2LSH>(a, pts->dtype, al, rc, ch, waves * kWave, lds, s, nblk, dry)
+                   : launch_fam<LSH_SRP>(a, pts->dtype, al, rc, ch, waves * kWave, lds, s, nblk, dry);
+    };
+    hipError_t e = launch_hash(true);
+    if (e != hipSuccess)
+        LSH_FAIL(LSH_EHIP, "hash kernel set-up failed: %s", hip_msg(e));
     if (rc) {
         WsLayout wl = ws_layout(pts->d, a.m);
         if (!ws || ws_bytes < wl.total)
@@ -1311,9 +1342,7 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         LSH_LAUNCHED("csr_kernel");
     }
 
-    hipError_t e = disc->family == LSH_E2LSH
-                       ? launch_fam<LSH_E2LSH>(a, pts->dtype, al, rc, ch, waves * kWave, lds, s, nblk)
-                       : launch_fam<LSH_SRP>(a, pts->dtype, al, rc, ch, waves * kWave, lds, s, nblk);
+    e = launch_hash(false);
     if (e != hipSuccess)
         LSH_FAIL(LSH_EHIP, "hash kernel launch failed: %s", hip_msg(e));
     return LSH_OK;

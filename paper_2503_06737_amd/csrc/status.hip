@@ -38,4 +38,4 @@ int device_cu_count()
 
 extern "C" const char *lsh_last_error(void) { return lsh::g_err; }
 
-extern "C" int32_t lsh_version(void) { return 100; }
+extern "C" int32_t lsh_version(void) { return 200; }

@@ -40,7 +40,8 @@ class Points(C.Structure):
 
 class Disc(C.Structure):
     _fields_ = [("family", C.c_int32), ("m", C.c_int32), ("K", C.c_int32), ("L", C.c_int32),
-                ("w", C.c_float), ("b", C.c_void_p), ("recheck", C.c_int32)]
+                ("w", C.c_float), ("b", C.c_void_p), ("recheck", C.c_int32),
+                ("comp_slot", C.c_void_p)]
 
 
 class Out(C.Structure):
@@ -120,8 +121,9 @@ def points(x: torch.Tensor, scale: torch.Tensor | None = None) -> Points:
                   x.shape[0], x.shape[1], x.stride(0) if x.shape[0] > 1 else x.shape[1])
 
 
-def _disc(family, K, L, w, b, recheck):
-    return Disc(family, K * L, K, L, float(w), None if b is None else b.data_ptr(), int(recheck))
+def _disc(family, K, L, w, b, recheck, comp_slot=None):
+    return Disc(family, K * L, K, L, float(w), None if b is None else b.data_ptr(), int(recheck),
+                None if comp_slot is None else comp_slot.data_ptr())
 
 
 def _outputs(n, m, L, device, keys, codes, proj, counters):
@@ -135,23 +137,26 @@ def _outputs(n, m, L, device, keys, codes, proj, counters):
 
 
 def lsh_hash_cs(x, h, s, *, family, K, L, w=1.0, b=None, scale=None, recheck=False, keys=True,
-                codes=False, proj=False, counters=None):
+                codes=False, proj=False, counters=None, comp_slot=None):
     """CS-E2LSH / CS-SRP of the rows of x.  Returns dict(keys [L][n] int64 bit
-    patterns of the u64 keys, codes [n][m], proj [n][m], counters)."""
+    patterns of the u64 keys, codes [n][m], proj [n][m], counters).
+    comp_slot: optional [m] device tensor, the code position of each sketch
+    component (a permutation of range(m))."""
     pts = points(x, scale)
     m = K * L
     o, out = _outputs(x.shape[0], m, L, x.device, keys, codes, proj, counters)
     wsb = lib().lsh_hash_workspace_bytes(x.shape[1], m, int(recheck))
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=x.device)
-    disc = _disc(family, K, L, w, b, recheck)
+    disc = _disc(family, K, L, w, b, recheck, comp_slot)
     _check(lib().lsh_hash_cs(C.byref(pts), _ptr(h), _ptr(s), C.byref(disc), C.byref(out),
                              _ptr(ws), wsb, _stream()))
     return o
 
 
 def lsh_hash_hcs(x, dk, mk, hk, sk, *, family, K, L, w=1.0, b=None, scale=None, recheck=False,
-                 keys=True, codes=False, proj=False, counters=None):
-    """HCS-E2LSH / HCS-SRP.  hk/sk: device tensors with the per-mode tables back to back."""
+                 keys=True, codes=False, proj=False, counters=None, comp_slot=None):
+    """HCS-E2LSH / HCS-SRP.  hk/sk: device tensors with the per-mode tables back
+    to back; comp_slot as for lsh_hash_cs."""
     pts = points(x, scale)
     m = K * L
     assert math.prod(mk) == m
@@ -161,7 +166,7 @@ def lsh_hash_hcs(x, dk, mk, hk, sk, *, family, K, L, w=1.0, b=None, scale=None, 
     mka = (C.c_int32 * N)(*mk)
     wsb = lib().lsh_hash_workspace_bytes(x.shape[1], m, int(recheck))
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=x.device)
-    disc = _disc(family, K, L, w, b, recheck)
+    disc = _disc(family, K, L, w, b, recheck, comp_slot)
     _check(lib().lsh_hash_hcs(C.byref(pts), N, dka, mka, _ptr(hk), _ptr(sk), C.byref(disc),
                               C.byref(out), _ptr(ws), wsb, _stream()))
     return o

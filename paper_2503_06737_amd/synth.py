@@ -115,6 +115,12 @@ def hcs_state(dk, mk, seed: int):
     return hk, sk
 
 
+def component_slots(m: int, seed: int) -> np.ndarray:
+    """A uniformly random permutation of range(m): code position of each sketch
+    component (which components form which table)."""
+    return _rng(seed, 0x510).permutation(m).astype(np.uint32)
+
+
 def shifts(m: int, w: float, seed: int) -> np.ndarray:
     """b_l ~ U[0, w) as float32, one per hashcode component."""
     g = _rng(seed, 0xB0)
@@ -194,6 +200,9 @@ class Workload:
     def hcs_state(self, i: int):
         dk, mk = self.hcs[i]
         return hcs_state(dk, mk, self.seed + 1)
+
+    def slots(self) -> np.ndarray:
+        return component_slots(self.m, self.seed + 1)
 
     def b(self) -> np.ndarray:
         return shifts(self.m, self.w, self.seed + 1)

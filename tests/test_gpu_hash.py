@@ -245,3 +245,101 @@ def test_dense_with_cs_matrix_equals_cs():
     ys = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=1, K=K, L=L, proj=True)
     yd = lsh.lsh_hash_dense(to_dev(x), to_dev(R), family=1, K=K, L=L, proj=True)
     np.testing.assert_allclose(to_host(yd["proj"]), to_host(ys["proj"]), rtol=0, atol=1e-4)
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+@pytest.mark.parametrize("dk,mk", [((64, 64), (32, 32)), ((16, 16, 16), (8, 8, 16)),
+                                   ((8, 10, 12), (4, 4, 8))])
+def test_hcs_component_slots_parity(dk, mk, family):
+    """HCS with a seeded permutation assigning sketch components to tables:
+    projection, codes and keys against the oracle (fast path within the
+    near-edge band, recheck exact)."""
+    dev()
+    d = int(np.prod(dk))
+    m = int(np.prod(mk))
+    K = 16 if m % 16 == 0 else 8
+    L = m // K
+    n = 1500
+    x = synth.gaussian_clusters(n, d, 30, 0.2, 300 + d)
+    hk, sk = synth.hcs_state(dk, mk, 301 + d)
+    slot = synth.component_slots(m, 302 + d)
+    b = synth.shifts(m, 4.0, 303)
+    x64 = x.astype(np.float64)
+    ref = oracle.hash_points(x64, family, K, L, kind="hcs", w=4.0, b=b, dk=dk, mk=mk, hk=hk,
+                             sk=sk, comp_slot=slot)
+    args = (to_dev(x), dk, mk, to_dev(np.concatenate(hk)), to_dev(np.concatenate(sk)))
+    kw = dict(family=family, K=K, L=L, w=4.0, b=to_dev(b), comp_slot=to_dev(slot))
+    out = lsh.lsh_hash_hcs(*args, codes=True, proj=True, **kw)
+    compare_hash(out, ref, x64, K, L, what=f"hcs slots {dk}")
+    cnt = to_dev(np.zeros(4, np.uint64))
+    out = lsh.lsh_hash_hcs(*args, codes=True, recheck=True, counters=cnt, **kw)
+    compare_hash(out, ref, x64, K, L, exact=True, what=f"hcs slots {dk} recheck")
+    assert to_host(cnt, np.uint64)[3] == 0
+
+
+def test_cs_component_slots_parity():
+    """A component map on the count sketch: keys-only, codes and recheck."""
+    dev()
+    n, d, K, L = 5000, 784, 16, 64
+    x, h, s, b = _cs_case(n, d, K, L, "sparse", 404)
+    slot = synth.component_slots(K * L, 405)
+    x64 = x.astype(np.float64)
+    for fam in (oracle.E2LSH, oracle.SRP):
+        ref = oracle.hash_points(x64, fam, K, L, kind="cs", w=4.0, b=b, h=h, s=s, comp_slot=slot)
+        kw = dict(family=fam, K=K, L=L, w=4.0, b=to_dev(b), comp_slot=to_dev(slot))
+        out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), **kw)
+        compare_hash(out, ref, x64, K, L, what="cs slots keys only")
+        out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), codes=True, recheck=True, **kw)
+        compare_hash(out, ref, x64, K, L, exact=True, what="cs slots recheck")
+
+
+def test_c3_hcs_index_has_no_constant_table():
+    """The 4096-dimensional tensor-reshape workload with its own hash state:
+    with contiguous tables some tables give every point one bucket; with the
+    workload's component map no table does, and the index of the GPU keys
+    equals the oracle's."""
+    dev()
+    wl = synth.C3
+    n = 20000
+    x = wl.points(n)
+    b = wl.b()
+    slot = wl.slots()
+    xd = to_dev(x)
+    for i, (dk, mk) in enumerate(wl.hcs):
+        hk, sk = wl.hcs_state(i)
+        args = (xd, dk, mk, to_dev(np.concatenate(hk)), to_dev(np.concatenate(sk)))
+        kw = dict(family=oracle.E2LSH, K=wl.K, L=wl.L, w=wl.w, b=to_dev(b))
+        plain = lsh.lsh_build_index(lsh.lsh_hash_hcs(*args, **kw)["keys"])
+        assert (to_host(plain.arrays()[3]) == 1).sum() > 0, f"{dk}: contiguous tables"
+        keys = lsh.lsh_hash_hcs(*args, comp_slot=to_dev(slot), **kw)["keys"]
+        idx = lsh.lsh_build_index(keys)
+        nu = to_host(idx.arrays()[3])
+        assert (nu > 1).all(), f"{dk}: constant tables {np.nonzero(nu == 1)[0]}"
+        rk = oracle.hash_points(x.astype(np.float64), oracle.E2LSH, wl.K, wl.L, kind="hcs",
+                                w=wl.w, b=b, dk=dk, mk=mk, hk=hk, sk=sk, comp_slot=slot)
+        tab_near = rk["near"].reshape(n, wl.L, wl.K).any(axis=2).T
+        kg = to_host(keys, np.uint64)
+        assert not ((kg != rk["keys"]) & ~tab_near).any()
+        ref = oracle.build_index(kg)
+        assert (to_host(idx.arrays()[0], np.uint32) == ref["sorted_ids"]).all()
+        assert (nu == ref["nuniq"]).all()
+
+
+def test_invalid_hash_state_is_counted():
+    """counters[3] counts coordinates whose hash state is out of range (each is
+    taken as 0), once per call."""
+    dev()
+    n, d, K, L = 3000, 256, 8, 4
+    x, h, s, b = _cs_case(n, d, K, L, "clusters", 406)
+    h = h.copy()
+    h[[3, 77, 200]] = K * L + np.array([0, 5, 1000])
+    cnt = to_dev(np.zeros(4, np.uint64))
+    lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=1, K=K, L=L, counters=cnt)
+    assert to_host(cnt, np.uint64).tolist() == [0, 0, 0, 3]
+    slot = synth.component_slots(K * L, 407)
+    slot[5] = K * L
+    h2, _ = synth.cs_state(d, K * L, 408)
+    cnt = to_dev(np.zeros(4, np.uint64))
+    lsh.lsh_hash_cs(to_dev(x), to_dev(h2), to_dev(s), family=1, K=K, L=L, counters=cnt,
+                    comp_slot=to_dev(slot))
+    assert to_host(cnt, np.uint64)[3] == (h2 == 5).sum()

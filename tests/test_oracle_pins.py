@@ -214,6 +214,76 @@ def test_hcs_exact_moments_enumeration(orc):
 
 
 # ---------------------------------------------------------------------------
+# assignment of sketch components to tables (reading of which components form
+# a table; the paper leaves it open)
+# ---------------------------------------------------------------------------
+
+def test_assign_components_permutation_matrix(orc):
+    """Position slot[l] receives component l: y' = y P with P[l, slot[l]] = 1,
+    and the identity map leaves y unchanged; hand case m = 4."""
+    y = np.array([[10.0, 20.0, 30.0, 40.0]])
+    out = orc.assign_components(y, np.array([2, 0, 3, 1]))
+    assert out.tolist() == [[20.0, 40.0, 10.0, 30.0]]
+    g = np.random.default_rng(23)
+    m = 48
+    y = g.standard_normal((5, m))
+    slot = g.permutation(m)
+    P = np.zeros((m, m))
+    P[np.arange(m), slot] = 1.0
+    assert (orc.assign_components(y, slot) == y @ P).all()
+    assert (orc.assign_components(y, np.arange(m)) == y).all()
+
+
+def test_hcs_with_slots_is_cs_under_composite_slot_hash(orc):
+    """HCS followed by the component map equals a count sketch whose bin of
+    coordinate j is slot[composite bin(j)] (Definition def_hcs)."""
+    dk, mk = (4, 3, 5), (2, 3, 2)
+    hk, sk = _hcs_state(dk, mk, 24)
+    slot = np.random.default_rng(25).permutation(12)
+    hb, sb = np.zeros(60, int), np.zeros(60, int)
+    for j in range(60):
+        i1, i2, i3 = j % 4, (j // 4) % 3, j // 12
+        hb[j] = slot[hk[0][i1] + mk[0] * (hk[1][i2] + mk[1] * hk[2][i3])]
+        sb[j] = sk[0][i1] * sk[1][i2] * sk[2][i3]
+    x = np.random.default_rng(26).integers(-20, 20, (3, 60)).astype(float)
+    b = np.zeros(12, np.float32)
+    a = orc.hash_points(x, orc.SRP, 3, 4, kind="hcs", dk=dk, mk=mk, hk=hk, sk=sk,
+                        comp_slot=slot)
+    c = orc.hash_points(x, orc.SRP, 3, 4, kind="cs", h=hb, s=sb)
+    assert (a["y"] == c["y"]).all() and (a["keys"] == c["keys"]).all()
+    e = orc.hash_points(x, orc.E2LSH, 3, 4, kind="hcs", dk=dk, mk=mk, hk=hk, sk=sk, w=2.0, b=b,
+                        comp_slot=slot)
+    f = orc.hash_points(x, orc.E2LSH, 3, 4, kind="cs", h=hb, s=sb, w=2.0, b=b)
+    assert (e["codes"] == f["codes"]).all() and (e["keys"] == f["keys"]).all()
+
+
+def _structurally_zero_tables(dk, mk, hk, K, slot):
+    """Tables all of whose code positions hold a sketch component that no
+    input index reaches (some mode bin l_k with no i_k mapped to it)."""
+    hit = [np.bincount(h, minlength=m) > 0 for h, m in zip(hk, mk)]
+    live = hit[0]
+    for k in range(1, len(dk)):
+        live = np.concatenate([live & hk_live for hk_live in hit[k]])   # l = l_1 + m_1 l_2 + ...
+    pos_live = np.zeros(live.size, bool)
+    pos_live[slot] = live
+    return int((~pos_live.reshape(-1, K).any(axis=1)).sum())
+
+
+def test_c3_tables_not_constant_with_slots():
+    """The 500k x 4096 tensor-reshape workload, K = 16, L = 64: with contiguous
+    tables some tables sit inside one empty mode bin (every point gets the same
+    code there); with the workload's seeded component map none does."""
+    from paper_2503_06737_amd import synth
+    wl = synth.C3
+    slot = wl.slots()
+    for i in range(len(wl.hcs)):
+        dk, mk = wl.hcs[i]
+        hk, _ = wl.hcs_state(i)
+        assert _structurally_zero_tables(dk, mk, hk, wl.K, np.arange(wl.m)) > 0
+        assert _structurally_zero_tables(dk, mk, hk, wl.K, slot) == 0
+
+
+# ---------------------------------------------------------------------------
 # dense projection (Section 3.1, Definitions e2lsh and srp)
 # ---------------------------------------------------------------------------
 
