@@ -149,6 +149,20 @@ lsh_status lsh_hash_cs(const lsh_points *pts, const uint32_t *h, const int8_t *s
                        const lsh_disc *disc, const lsh_out *out, void *workspace,
                        size_t ws_bytes, void *stream);
 
+/* lsh_hash_cs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation, arguments and outputs as lsh_hash_cs, without the
+ * workspace.  With recheck = 1 the recheck's table (the CSR of h) is kept in
+ * a static device array of 197,120 bytes per GPU, held until the process
+ * ends; the call allocates and frees nothing.  Limits with recheck = 1:
+ * d <= 32768 and m <= 16384, else EINVAL.  Every call on one GPU shares that
+ * GPU's array and overwrites it, so calls with recheck = 1 that overlap on
+ * one GPU (on different streams, or from different threads before the first
+ * completes) race and give wrong codes; serialise them on one stream.  The
+ * caller still owns and passes the inputs and outputs. */
+lsh_status lsh_hash_cs_noalloc(const lsh_points *pts, const uint32_t *h, const int8_t *s,
+                               const lsh_disc *disc, const lsh_out *out, void *stream);
+
 /* HCS-E2LSH / HCS-SRP (Definitions HCS_Eucl_LSH and hcs_consine_lsh).  The
  * point is read as an N-order tensor d_1 x ... x_N (first mode fastest,
  * zero-padded at the end when d < prod d_k, as in Section 6) and sketched

@@ -39,6 +39,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
+
 #include "lsh_internal.h"
 
 namespace lsh {
@@ -1368,6 +1370,75 @@ extern "C" lsh_status lsh_hash_cs(const lsh_points *pts, const uint32_t *h, cons
     a.h = h;
     a.s = s;
     return lsh::hash_common(pts, a, disc, out, workspace, ws_bytes, stream);
+}
+
+namespace lsh {
+namespace {
+
+// Scratch of lsh_hash_cs_noalloc: the recheck's CSR of h at its largest
+// (d = 32768 coordinates, m = 16384 bins), one copy per GPU for the life of
+// the process.  In host code `scratch` names a host-side stand-in; only the
+// address that hipGetSymbolAddress returns for the current device is used.
+constexpr size_t kScratchBytes = 256 + 65792 + 131072;
+static_assert(kScratchBytes >= 256 + ((16384 + 1) * 4 + 255) / 256 * 256 + kCsrMaxD * 4,
+              "scratch too small for the largest recheck CSR");
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch, looked up once per device.
+lsh_status scratch_ptr(void **out)
+{
+    int dev = 0;
+    LSH_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        LSH_FAIL(LSH_EINVAL, "device %d is beyond the %d the static scratch supports", dev,
+                 kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            LSH_FAIL(LSH_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                     hip_msg(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LSH_OK;
+}
+
+} // namespace
+} // namespace lsh
+
+extern "C" lsh_status lsh_hash_cs_noalloc(const lsh_points *pts, const uint32_t *h, const int8_t *s,
+                                          const lsh_disc *disc, const lsh_out *out, void *stream)
+{
+    if (!h || !s)
+        LSH_FAIL(LSH_EINVAL, "h and s are required");
+    if (!pts || !disc)
+        LSH_FAIL(LSH_EINVAL, "points and discretisation descriptors are required");
+    void *ws = nullptr;
+    size_t wsb = 0;
+    if (disc->recheck) {
+        if (pts->d < 1 || pts->d > lsh::kCsrMaxD || disc->m < 1 || disc->m > 16384)
+            LSH_FAIL(LSH_EINVAL,
+                     "no-allocation recheck needs 1 <= d <= %d and 1 <= m <= 16384 (d=%d m=%d)",
+                     lsh::kCsrMaxD, pts->d, disc->m);
+        wsb = lsh::ws_layout(pts->d, disc->m).total;
+        if (wsb > lsh::kScratchBytes)
+            LSH_FAIL(LSH_EINVAL, "recheck needs %zu bytes of scratch, the static array holds %zu",
+                     wsb, lsh::kScratchBytes);
+        lsh_status st = lsh::scratch_ptr(&ws);
+        if (st != LSH_OK)
+            return st;
+    }
+    lsh::HashArgs a = {};
+    a.hcs = 0;
+    a.h = h;
+    a.s = s;
+    return lsh::hash_common(pts, a, disc, out, ws, wsb, stream);
 }
 
 extern "C" lsh_status lsh_hash_hcs(const lsh_points *pts, int32_t N, const int32_t *d_k,

@@ -22,7 +22,7 @@ E2LSH, SRP = 0, 1
 F32, BF16, FP8 = 0, 1, 2
 STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ENOMEM", -3: "LSH_EHIP", -5: "LSH_ERANGE"}
 
-EXPORTS = ("lsh_hash_workspace_bytes", "lsh_hash_cs", "lsh_hash_hcs", "lsh_hash_dense",
+EXPORTS = ("lsh_hash_workspace_bytes", "lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense",
            "lsh_index_bytes", "lsh_build_workspace_bytes", "lsh_build_index",
            "lsh_index_get_view", "lsh_index_free", "lsh_query", "lsh_last_error", "lsh_version")
 
@@ -70,6 +70,7 @@ def lib() -> C.CDLL:
         L.lsh_hash_workspace_bytes.argtypes = [i32, i32, i32]
         L.lsh_hash_workspace_bytes.restype = sz
         L.lsh_hash_cs.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+        L.lsh_hash_cs_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lsh_hash_hcs.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.lsh_hash_dense.argtypes = [vp, vp, vp, vp, vp]
         L.lsh_index_bytes.argtypes = [i64, i32]
@@ -84,7 +85,7 @@ def lib() -> C.CDLL:
         L.lsh_query.argtypes = [vp, i32, vp, vp, vp, i64, i32, i64, i32, vp, vp, vp, vp]
         L.lsh_last_error.restype = C.c_char_p
         L.lsh_version.restype = i32
-        for fn in ("lsh_hash_cs", "lsh_hash_hcs", "lsh_hash_dense", "lsh_build_index",
+        for fn in ("lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense", "lsh_build_index",
                    "lsh_index_get_view", "lsh_query", "lsh_build_check"):
             getattr(L, fn).restype = i32
         _lib = L
@@ -150,6 +151,22 @@ def lsh_hash_cs(x, h, s, *, family, K, L, w=1.0, b=None, scale=None, recheck=Fal
     disc = _disc(family, K, L, w, b, recheck, comp_slot)
     _check(lib().lsh_hash_cs(C.byref(pts), _ptr(h), _ptr(s), C.byref(disc), C.byref(out),
                              _ptr(ws), wsb, _stream()))
+    return o
+
+
+def lsh_hash_cs_noalloc(x, h, s, out, *, family, K, L, w=1.0, b=None, scale=None, recheck=False,
+                        comp_slot=None):
+    """lsh_hash_cs without a workspace: the recheck table lives in the library's
+    static device array.  out: dict of caller-allocated device tensors (keys
+    [L][n] int64, codes [n][m] int32, proj [n][m] float32, counters [4] int64;
+    any may be absent or None); this call allocates nothing."""
+    pts = points(x, scale)
+    o = {k: out.get(k) for k in ("keys", "codes", "proj", "counters")}
+    c = Out(_ptr(o["keys"]), x.shape[0] if o["keys"] is None else o["keys"].stride(0),
+            _ptr(o["codes"]), _ptr(o["proj"]), _ptr(o["counters"]))
+    disc = _disc(family, K, L, w, b, recheck, comp_slot)
+    _check(lib().lsh_hash_cs_noalloc(C.byref(pts), _ptr(h), _ptr(s), C.byref(disc), C.byref(c),
+                                     _stream()))
     return o
 
 
