@@ -135,6 +135,26 @@ typedef struct lsh_out {
  *       z *= 0xbf58476d1ce4e5b9; z ^= z>>27; z *= 0x94d049bb133111eb; z ^= z>>31.
  */
 
+/* ---------------------------------------------------------------- storage */
+
+/* Store n FP32 rows x[i*ldx + j] (j < d) as low-precision codes with one FP32
+ * scale per row, the form lsh_points reads with dtype LSH_BF16 or
+ * LSH_FP8_E4M3FN.  The paper fixes no storage precision; this is the storage
+ * of the precision path (value = row_scale[i] * decoded code).
+ *   LSH_BF16:       row_scale[i] = max_j |x_ij| (1 for a zero row);
+ *                   q[i*ldq + j] = bf16(x_ij / row_scale[i]) as uint16 bits.
+ *   LSH_FP8_E4M3FN: row_scale[i] = max_j |x_ij| / 448 (1 for a zero row);
+ *                   q[i*ldq + j] = e4m3fn(clamp(x_ij / row_scale[i], -448, 448))
+ *                   as uint8 bits.
+ * Each division is a binary32 division rounded to nearest even, and each
+ * conversion rounds to the nearest code, ties to the even code (a negative
+ * zero or a negative value that rounds to zero keeps its sign bit).
+ * x, q, row_scale: device arrays owned by the caller; x must hold finite
+ * values (a NaN or infinity makes its row's codes and scale unspecified).
+ * EINVAL on a bad shape (d < 1, ldx < d, ldq < d) or another dtype. */
+lsh_status lsh_quantize_rows(const float *x, int64_t n, int32_t d, int64_t ldx, int32_t dtype,
+                             void *q, int64_t ldq, float *row_scale, void *stream);
+
 /* ---------------------------------------------------------------- hashing */
 
 /* Workspace bytes for lsh_hash_cs / lsh_hash_hcs (0 unless recheck = 1). */
@@ -235,6 +255,16 @@ void lsh_index_free(lsh_index *idx);
  * lsh_build_workspace_bytes(n, L); EHIP if the copy fails. */
 lsh_status lsh_build_check(const void *workspace, size_t ws_bytes, int64_t n, int32_t L,
                            uint32_t counts[2], void *stream);
+
+/* lsh_build_check without the wait: enqueues on `stream` the copies of the
+ * two counters into counts[0..1] (device memory or pinned host memory owned
+ * by the caller) and returns; they are valid once the stream reaches them.
+ * Meant for a server that checks each build beside its completion event.
+ * For n = 0 nothing is enqueued and counts is not written (no build kernels
+ * ran: both counts are zero).  EINVAL as lsh_build_check; EHIP if a copy
+ * cannot be enqueued. */
+lsh_status lsh_build_check_async(const void *workspace, size_t ws_bytes, int64_t n, int32_t L,
+                                 uint32_t *counts, void *stream);
 
 /* ------------------------------------------------------------------ query */
 

@@ -45,6 +45,7 @@ def _p(a):
 def _declare(L):
     vp, i64, i32, f32, f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_float, C.c_double
     L.orc_decode.argtypes = [vp, C.c_int, vp, i64, i32, i64, vp]
+    L.orc_quantise_rows.argtypes = [vp, i64, i32, C.c_int, vp, vp]
     L.orc_cs_sketch.argtypes = [vp, i64, i32, vp, vp, i32, vp]
     L.orc_hcs_sketch.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp]
     L.orc_dense_proj.argtypes = [vp, i64, i32, vp, i32, vp]
@@ -84,6 +85,19 @@ def decode(q: np.ndarray, scale: np.ndarray | None = None) -> np.ndarray:
     x = np.empty((n, d), np.float64)
     lib().orc_decode(_p(q), dt, None if sc is None else _p(sc), n, d, d, _p(x))
     return x
+
+
+def quantise_rows(x: np.ndarray, kind: str):
+    """FP32 rows -> (codes, scale): BF16 (uint16 bits, scale = max|x|) or
+    FP8-E4M3FN (uint8 bits, scale = max|x| / 448); each value x / scale
+    rounded to the nearest code, ties to even (the low-precision storage)."""
+    x = np.ascontiguousarray(x, np.float32)
+    n, d = x.shape
+    dt = {"bf16": BF16, "fp8": FP8}[kind]
+    q = np.empty((n, d), np.uint16 if dt == BF16 else np.uint8)
+    sc = np.empty(n, np.float32)
+    lib().orc_quantise_rows(_p(x), n, d, dt, _p(q), _p(sc))
+    return q, sc
 
 
 def fp8_value(bits: int) -> float:

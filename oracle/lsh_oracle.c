@@ -87,6 +87,76 @@ void orc_decode(const void *q, int dtype, const float *row_scale, int64_t n, int
     }
 }
 
+/* Storing FP32 rows in low precision (the precision path; the paper fixes no
+ * storage precision).  Per row: scale = max|x| for BF16, max|x| / 448 for
+ * FP8-E4M3FN (1 for a zero row), both in binary32; each stored value is the
+ * binary32 quotient x / scale (FP8: clamped to [-448, 448]) rounded to the
+ * nearest code, ties to the code with an even last bit.  The nearest code is
+ * found by comparing the candidate values exactly in FP64. */
+
+/* Nearest BF16 pattern: the two BF16 values around v are its binary32 bits
+ * truncated to the upper half and that plus one unit in the last place. */
+static uint16_t nearest_bf16(float v)
+{
+    uint32_t u;
+    memcpy(&u, &v, sizeof u);
+    uint16_t lo = (uint16_t)(u >> 16), hi = (uint16_t)(lo + 1);
+    double dv = (double)v;
+    double dlo = fabs(dv - bf16_value(lo)), dhi = fabs(bf16_value(hi) - dv);
+    if (dlo < dhi)
+        return lo;
+    if (dhi < dlo)
+        return hi;
+    return (lo & 1) ? hi : lo;
+}
+
+/* Nearest E4M3FN pattern by search over every finite non-negative code
+ * (0x00..0x7e); the sign bit is that of v. */
+static uint8_t nearest_e4m3fn(float v)
+{
+    double a = fabs((double)v);
+    int best = 0;
+    double bd = INFINITY;
+    for (int c = 0; c <= 0x7e; ++c) {
+        double dd = fabs(orc_fp8_e4m3fn_value((uint8_t)c) - a);
+        if (dd < bd || (dd == bd && (c & 1) == 0 && (best & 1) == 1)) {
+            bd = dd;
+            best = c;
+        }
+    }
+    return (uint8_t)((signbit(v) ? 0x80 : 0) | best);
+}
+
+void orc_quantise_rows(const float *x, int64_t n, int32_t d, int dtype, void *q, float *scale)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const float *xr = x + i * (int64_t)d;
+        float amax = 0.0f;
+        for (int32_t j = 0; j < d; ++j)
+            if (fabsf(xr[j]) > amax)
+                amax = fabsf(xr[j]);
+        float sc;
+        if (dtype == ORC_BF16)
+            sc = amax > 0.0f ? amax : 1.0f;
+        else
+            sc = amax > 0.0f ? amax / 448.0f : 1.0f;
+        scale[i] = sc;
+        for (int32_t j = 0; j < d; ++j) {
+            float v = xr[j] / sc;
+            if (dtype == ORC_BF16) {
+                ((uint16_t *)q)[i * (int64_t)d + j] = nearest_bf16(v);
+            } else {
+                if (v > 448.0f)
+                    v = 448.0f;
+                if (v < -448.0f)
+                    v = -448.0f;
+                ((uint8_t *)q)[i * (int64_t)d + j] = nearest_e4m3fn(v);
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* 2. projections                                                            */
 /* ------------------------------------------------------------------------ */

@@ -1912,6 +1912,33 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     return LSH_OK;
 }
 
+extern "C" lsh_status lsh_build_check_async(const void *ws, size_t ws_bytes, int64_t n, int32_t L,
+                                            uint32_t *counts, void *stream)
+{
+    using namespace lsh;
+    if (!counts)
+        LSH_FAIL(LSH_EINVAL, "counts is NULL");
+    if (n < 0 || L < 1)
+        LSH_FAIL(LSH_EINVAL, "bad n=%lld L=%d", (long long)n, L);
+    if (n == 0)
+        return LSH_OK; // no build kernels ran; counts is not written
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    const WsLayout wl = ws_layout(n, L);
+    if (!ws || ws_bytes < wl.total)
+        LSH_FAIL(LSH_EINVAL, "workspace needs %zu bytes, got %zu", wl.total, ws_bytes);
+    const unsigned char *wb = (const unsigned char *)ws;
+    // the same places lsh_build_index gives the counters
+    const uint32_t *overflows = (const uint32_t *)(wb + wl.bcount) + 1;
+    const uint32_t *waits =
+        (const uint32_t *)((const uint64_t *)(wb + wl.hstat) + (size_t)L * wl.nhtiles) +
+        16 * (size_t)L;
+    if ((e = hipMemcpyAsync(&counts[0], overflows, 4, hipMemcpyDefault, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&counts[1], waits, 4, hipMemcpyDefault, s)) != hipSuccess)
+        LSH_FAIL(LSH_EHIP, "lsh_build_check: %s", hip_msg(e));
+    return LSH_OK;
+}
+
 extern "C" lsh_status lsh_build_check(const void *ws, size_t ws_bytes, int64_t n, int32_t L,
                                       uint32_t counts[2], void *stream)
 {
@@ -1923,23 +1950,12 @@ extern "C" lsh_status lsh_build_check(const void *ws, size_t ws_bytes, int64_t n
         LSH_FAIL(LSH_EINVAL, "bad n=%lld L=%d", (long long)n, L);
     if (n == 0)
         return LSH_OK; // no build kernels ran
-    const WsLayout wl = ws_layout(n, L);
-    if (!ws || ws_bytes < wl.total)
-        LSH_FAIL(LSH_EINVAL, "workspace needs %zu bytes, got %zu", wl.total, ws_bytes);
-    const unsigned char *wb = (const unsigned char *)ws;
-    // the same places lsh_build_index gives the counters
-    const uint32_t *overflows = (const uint32_t *)(wb + wl.bcount) + 1;
-    const uint32_t *waits =
-        (const uint32_t *)((const uint64_t *)(wb + wl.hstat) + (size_t)L * wl.nhtiles) +
-        16 * (size_t)L;
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e;
-    if ((e = hipMemcpyAsync(&counts[0], overflows, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(&counts[1], waits, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess) {
-        set_error("lsh_build_check: %s", hip_msg(e));
-        return LSH_EHIP;
-    }
+    lsh_status st = lsh_build_check_async(ws, ws_bytes, n, L, counts, stream);
+    if (st != LSH_OK)
+        return st;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess)
+        LSH_FAIL(LSH_EHIP, "lsh_build_check: %s", hip_msg(e));
     return LSH_OK;
 }
 

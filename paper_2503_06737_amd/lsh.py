@@ -22,7 +22,7 @@ E2LSH, SRP = 0, 1
 F32, BF16, FP8 = 0, 1, 2
 STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ENOMEM", -3: "LSH_EHIP", -5: "LSH_ERANGE"}
 
-EXPORTS = ("lsh_hash_workspace_bytes", "lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense",
+EXPORTS = ("lsh_quantize_rows", "lsh_build_check_async", "lsh_hash_workspace_bytes", "lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense",
            "lsh_index_bytes", "lsh_build_workspace_bytes", "lsh_build_index",
            "lsh_index_get_view", "lsh_index_free", "lsh_query", "lsh_last_error", "lsh_version")
 
@@ -82,11 +82,14 @@ def lib() -> C.CDLL:
         L.lsh_index_free.argtypes = [vp]
         L.lsh_index_free.restype = None
         L.lsh_build_check.argtypes = [vp, sz, i64, i32, vp, vp]
+        L.lsh_build_check_async.argtypes = [vp, sz, i64, i32, vp, vp]
+        L.lsh_quantize_rows.argtypes = [vp, i64, i32, i64, i32, vp, i64, vp, vp]
         L.lsh_query.argtypes = [vp, i32, vp, vp, vp, i64, i32, i64, i32, vp, vp, vp, vp]
         L.lsh_last_error.restype = C.c_char_p
         L.lsh_version.restype = i32
         for fn in ("lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense", "lsh_build_index",
-                   "lsh_index_get_view", "lsh_query", "lsh_build_check"):
+                   "lsh_index_get_view", "lsh_query", "lsh_build_check", "lsh_build_check_async",
+                   "lsh_quantize_rows"):
             getattr(L, fn).restype = i32
         _lib = L
     return _lib
@@ -120,6 +123,24 @@ def points(x: torch.Tensor, scale: torch.Tensor | None = None) -> Points:
         assert scale.dtype == torch.float32 and scale.is_contiguous()
     return Points(x.data_ptr() if x.numel() else 0, dt, None if scale is None else scale.data_ptr(),
                   x.shape[0], x.shape[1], x.stride(0) if x.shape[0] > 1 else x.shape[1])
+
+
+def lsh_quantize_rows(x: torch.Tensor, kind: str, q: torch.Tensor | None = None,
+                      scale: torch.Tensor | None = None):
+    """FP32 rows -> (codes, scale) on the device: kind "bf16" (int16 bit
+    patterns) or "fp8" (uint8 bit patterns), one float32 scale per row.
+    q / scale may be given (views into resident storage) to write in place."""
+    assert x.dtype == torch.float32 and x.dim() == 2 and x.stride(1) == 1
+    n, d = x.shape
+    dt = {"bf16": BF16, "fp8": FP8}[kind]
+    if q is None:
+        q = torch.empty((n, d), dtype=torch.int16 if dt == BF16 else torch.uint8, device=x.device)
+    if scale is None:
+        scale = torch.empty(n, dtype=torch.float32, device=x.device)
+    assert q.shape == (n, d) and q.stride(1) == 1 and scale.shape == (n,) and scale.is_contiguous()
+    _check(lib().lsh_quantize_rows(_ptr(x), n, d, x.stride(0) if n > 1 else d, dt, _ptr(q),
+                                   q.stride(0) if n > 1 else d, _ptr(scale), _stream()))
+    return q, scale
 
 
 def _disc(family, K, L, w, b, recheck, comp_slot=None):
@@ -215,6 +236,15 @@ class Index:
         _check(lib().lsh_build_check(_ptr(self.ws), self.ws.numel(), self.n, self.L, c,
                                      _stream()))
         return int(c[0]), int(c[1])
+
+    def check_async(self, counts: torch.Tensor):
+        """Enqueue the copy of this build's two consistency counters into
+        counts (int32 [2], pinned host or device) on the current stream."""
+        if self.ws is None:
+            raise ValueError("the build workspace was not kept")
+        assert counts.dtype == torch.int32 and counts.numel() == 2 and counts.is_contiguous()
+        _check(lib().lsh_build_check_async(_ptr(self.ws), self.ws.numel(), self.n, self.L,
+                                           _ptr(counts), _stream()))
 
     def view(self):
         v = IndexView()

@@ -4,33 +4,44 @@ The paper defines the index (Section 3.1) and the query by the union of a
 point's buckets (Section 3.1) re-ranked by exact distance (Section 6); it
 says nothing about serving.  This module runs that path as a service: query
 and insert requests arrive over time, and every kernel is a library call
-(`lsh_hash_cs`, `lsh_build_index`, `lsh_query`).
+(`lsh_quantize_rows`, `lsh_hash_cs`, `lsh_build_index`, `lsh_query`).
 
-* Requests are admitted first in, first out, into a batch whose projected
-  device bytes stay within an HBM budget.  A single request larger than the
-  budget runs alone.
-* A batch first commits its inserts: the points are appended to the
-  resident base, hashed, and indexed as a new segment whose ids continue
-  from the last segment.  Then it answers its queries against all segments.
+* Storage.  The resident base holds FP32 rows, or BF16 / FP8-E4M3FN codes
+  with one FP32 scale per row (quantised on the device as points arrive).
+  Hashing reads the stored form, so the index describes exactly the points
+  the re-rank scores; with ``recheck`` the hashcodes equal those of an FP64
+  evaluation over the stored (dequantised) values.
+* Admission.  Requests are admitted first in, first out, into a batch while
+  the transient device bytes of every batch in flight plus this one stay
+  within ``budget_bytes``, and the batch within its share of the budget
+  (``budget_bytes / max_inflight``), so that several batches are in flight
+  at once.  A request larger than the budget runs alone, once nothing else is
+  in flight.  Resident bytes (the base and the segments'
+  keys and indexes) are counted separately.
+* Streams.  Inserts run on one stream, in id order: the points are appended
+  to the base, hashed, and indexed as a new segment whose ids continue from
+  the last one.  Queries run on a pool of query streams; a batch's queries
+  wait on an event recorded after the latest insert, so they see every point
+  that arrived before them.  Batches on different streams overlap on the
+  device: one batch's re-rank runs beside the next batch's hashing and
+  index build.
 * A query sees exactly the inserts that arrived before it (its watermark).
   Queries of one batch are grouped by watermark, one `lsh_query` call per
   group, so a result never depends on how requests were batched.
 * At most 16 segments are live.  When an insert would make a 17th, the
   insert segments are merged by re-indexing their stored keys as one
   segment.
-* Up to `max_inflight` batches are enqueued on the stream at once, so the
-  host prepares batch i+1 while the GPU runs batch i.  A request's latency
-  runs from its arrival to the moment the host observes its batch's
-  completion event.
-
-Host copies of request points are part of the measured latency (the points
-arrive in host memory).
+* Each index build's consistency counters (`lsh_build_check_async`) are
+  copied to pinned memory beside the batch's completion event; a nonzero
+  count stops the server with `IndexBuildError`.
+* A request's latency runs from its arrival to the moment the host observes
+  its batch's completion event, and includes the host-to-device copy of its
+  points (they arrive in host memory).
 """
 from __future__ import annotations
 
 import math
 import time
-from collections import deque
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -39,6 +50,11 @@ import torch
 from . import lsh
 
 MAX_SEGMENTS = 16
+STORAGE = ("f32", "bf16", "fp8")
+
+
+class IndexBuildError(RuntimeError):
+    """An index build reported a nonzero consistency counter."""
 
 
 @dataclass
@@ -63,15 +79,33 @@ class Segment:
     keys: torch.Tensor      # [L][n] int64 on the device (kept for merges)
     index: lsh.Index
 
+    @property
+    def nbytes(self) -> int:
+        return self.keys.numel() * 8 + self.index.mem.numel()
+
 
 @dataclass
 class Stats:
     batches: int = 0
     merges: int = 0
-    peak_bytes: int = 0
+    peak_bytes: int = 0           # transient bytes of the batches in flight
+    peak_resident_bytes: int = 0  # base + segments
     points_hashed: int = 0
-    busy_s: float = 0.0
+    busy_s: float = 0.0           # union of the batches' device intervals
+    batch_time_s: float = 0.0     # sum of the batches' device intervals
+    max_inflight_seen: int = 0
+    builds_checked: int = 0
     batch_sizes: list = field(default_factory=list)
+
+
+@dataclass
+class _Inflight:
+    reqs: list
+    nbytes: int
+    ev_start: torch.cuda.Event
+    ev_end: torch.cuda.Event
+    held: list                    # segments the batch's queries read
+    checks: list                  # pinned int32 [2] build counters
 
 
 def poisson_stream(n_req: int, rate: float, query_frac: float, max_points: int, d: int,
@@ -95,43 +129,72 @@ def poisson_stream(n_req: int, rate: float, query_frac: float, max_points: int, 
 
 class Server:
     def __init__(self, base: torch.Tensor, h, s, b, *, K: int, L: int, w: float, capacity: int,
-                 budget_bytes: int, k: int = 10, metric: int = lsh.E2LSH, max_inflight: int = 2,
-                 recheck: bool = False):
+                 budget_bytes: int, k: int = 10, metric: int = lsh.E2LSH, max_inflight: int = 4,
+                 recheck: bool = False, storage: str = "f32", query_streams: int = 2):
+        """base: [n0][d] FP32 device tensor of the initial points (quantised
+        on the device when storage is "bf16" or "fp8")."""
+        if storage not in STORAGE:
+            raise ValueError(f"storage must be one of {STORAGE}")
         dev = base.device
+        self.device = dev
         self.recheck = recheck
+        self.storage = storage
         self.d = base.shape[1]
         self.K, self.L, self.w, self.k, self.metric = K, L, w, k, metric
         self.h, self.s, self.b = h, s, b
         self.budget = int(budget_bytes)
-        self.max_inflight = max_inflight
-        self.base = torch.empty((capacity, self.d), dtype=torch.float32, device=dev)
+        self.max_inflight = max(1, int(max_inflight))
+        elt = {"f32": torch.float32, "bf16": torch.int16, "fp8": torch.uint8}[storage]
+        self.base = torch.empty((capacity, self.d), dtype=elt, device=dev)
+        self.scale = (None if storage == "f32"
+                      else torch.empty(capacity, dtype=torch.float32, device=dev))
+        self.s_ins = torch.cuda.Stream(dev)
+        self.s_q = [torch.cuda.Stream(dev) for _ in range(max(1, query_streams))]
+        self._rr = 0
+        self._ins_done: torch.cuda.Event | None = None
         n0 = base.shape[0]
-        self.base[:n0] = base
-        self.n = n0
-        keys = self._hash(self.base[:n0])
-        self.segments: list[Segment] = [Segment(0, n0, keys, lsh.lsh_build_index(keys))]
+        self.n = 0
+        self.segments: list[Segment] = []
         self.stats = Stats()
+        self.s_ins.wait_stream(torch.cuda.current_stream(dev))   # base was written there
+        checks: list = []
+        with torch.cuda.stream(self.s_ins):
+            self._append(base, checks)
+        torch.cuda.synchronize(dev)
+        self._verify(checks)
         self.arrived_inserts = n0   # ids of everything that arrived so far (watermarks)
 
     # ------------------------------------------------------------- kernels
-    def _hash(self, x: torch.Tensor) -> torch.Tensor:
+    def _stored(self, lo: int, hi: int):
+        """(points, row scales) of base rows lo..hi in their stored form."""
+        return self.base[lo:hi], None if self.scale is None else self.scale[lo:hi]
+
+    def _hash(self, x: torch.Tensor, scale=None) -> torch.Tensor:
         return lsh.lsh_hash_cs(x, self.h, self.s, family=self.metric, K=self.K, L=self.L,
                                w=self.w, b=self.b if self.metric == lsh.E2LSH else None,
-                               recheck=self.recheck)["keys"]
+                               scale=scale, recheck=self.recheck)["keys"]
 
-    def _request_bytes(self, r: Request) -> int:
-        m = r.points.shape[0]
-        if r.kind == "query":
-            return m * (4 * self.d + 8 * self.L + 12 * self.k + 4)
-        return (m * 8 * self.L + lsh.lib().lsh_index_bytes(m, self.L)
-                + lsh.lib().lsh_build_workspace_bytes(m, self.L))
+    def _build(self, keys: torch.Tensor, id_base: int, checks: list) -> lsh.Index:
+        idx = lsh.lsh_build_index(keys, id_base=id_base)
+        chk = torch.zeros(2, dtype=torch.int32).pin_memory()
+        idx.check_async(chk)
+        checks.append(chk)
+        idx.ws = None   # the workspace is free once the copy is enqueued (same stream)
+        return idx
 
-    def _insert(self, pts: torch.Tensor) -> None:
+    def _append(self, pts: torch.Tensor, checks: list) -> None:
+        """Store FP32 device rows at the end of the base, hash them from their
+        stored form and index them as a new segment (on the current stream)."""
         m = pts.shape[0]
-        if self.n + m > self.base.shape[0]:
+        lo = self.n
+        if lo + m > self.base.shape[0]:
             raise RuntimeError("base capacity exhausted")
-        self.base[self.n:self.n + m] = pts
-        keys = self._hash(self.base[self.n:self.n + m])
+        if self.storage == "f32":
+            self.base[lo:lo + m] = pts
+        else:
+            lsh.lsh_quantize_rows(pts, self.storage, q=self.base[lo:lo + m],
+                                  scale=self.scale[lo:lo + m])
+        keys = self._hash(*self._stored(lo, lo + m))
         if len(self.segments) >= MAX_SEGMENTS:
             # merge every insert segment (ids are contiguous) and this one
             ins = self.segments[1:]
@@ -140,45 +203,111 @@ class Server:
             self.segments = self.segments[:1]
             self.stats.merges += 1
         else:
-            first = self.n
+            first = lo
         self.segments.append(Segment(first, keys.shape[1], keys,
-                                     lsh.lsh_build_index(keys, id_base=first)))
+                                     self._build(keys, first, checks)))
         self.n += m
 
-    def _run_batch(self, batch: list[Request], pinned) -> None:
+    # ---------------------------------------------------------- accounting
+    def _request_bytes(self, r: Request) -> int:
+        """Transient device bytes of one request: the points copied in, the
+        hash outputs and query results or the index-build workspace."""
+        m = r.points.shape[0]
+        L = self.L
+        if r.kind == "query":
+            return m * (4 * self.d + 8 * L + 12 * self.k + 4)
+        return m * 4 * self.d + lsh.lib().lsh_build_workspace_bytes(m, L)
+
+    def _merge_bytes(self, m_ins: int) -> int:
+        """Transient bytes of the merge an insert of m_ins points triggers (0 if none)."""
+        if m_ins == 0 or len(self.segments) < MAX_SEGMENTS:
+            return 0
+        nm = sum(sg.n for sg in self.segments[1:]) + m_ins
+        return nm * 8 * self.L + lsh.lib().lsh_build_workspace_bytes(nm, self.L)
+
+    def resident_bytes(self) -> int:
+        b = self.base.numel() * self.base.element_size()
+        if self.scale is not None:
+            b += self.scale.numel() * 4
+        return b + sum(sg.nbytes for sg in self.segments)
+
+    def _verify(self, checks: list) -> None:
+        for c in checks:
+            self.stats.builds_checked += 1
+            if int(c[0]) or int(c[1]):
+                raise IndexBuildError(f"index build counters {c.tolist()}: big-sort parts not "
+                                      "queued / run-head waits given up; the segment is wrong")
+
+    # --------------------------------------------------------------- batch
+    def _pinned(self, arrs: list) -> torch.Tensor:
+        """The requests' points copied once into one pinned buffer, then to
+        the device on the current stream (the host allocator keeps the
+        buffer until that copy is done)."""
+        m = sum(a.shape[0] for a in arrs)
+        host = torch.empty((m, self.d), dtype=torch.float32, pin_memory=True)
+        off = 0
+        for a in arrs:
+            host[off:off + a.shape[0]].copy_(torch.from_numpy(a))
+            off += a.shape[0]
+        return host.to(self.device, non_blocking=True)
+
+    def _run_batch(self, batch: list[Request], nbytes: int) -> _Inflight:
         ins = [r for r in batch if r.kind == "insert"]
         qs = [r for r in batch if r.kind == "query"]
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        checks: list = []
+        held: list = []
         if ins:
-            pts = pinned([r.points for r in ins])
-            self._insert(pts)
+            with torch.cuda.stream(self.s_ins):
+                ev0.record()
+                pts = self._pinned([r.points for r in ins])
+                self._append(pts, checks)
+                done = torch.cuda.Event()
+                done.record()
+                self._ins_done = done
             self.stats.points_hashed += pts.shape[0]
         if qs:
-            Q = pinned([r.points for r in qs])
-            qk = self._hash(Q)
-            self.stats.points_hashed += Q.shape[0]
-            lo = 0
-            while lo < len(qs):     # one call per watermark group
-                hi = lo
-                while hi < len(qs) and qs[hi].watermark == qs[lo].watermark:
-                    hi += 1
-                a = sum(r.points.shape[0] for r in qs[:lo])
-                z = a + sum(r.points.shape[0] for r in qs[lo:hi])
-                segs = [sg.index for sg in self.segments if sg.id_base < qs[lo].watermark]
-                ids, sc, nc = lsh.lsh_query(segs, self.base[:self.n], Q[a:z], qk[:, a:z],
-                                            k=self.k, watermark=qs[lo].watermark,
-                                            metric=self.metric)
-                off = 0
-                for r in qs[lo:hi]:
-                    m = r.points.shape[0]
-                    r.ids, r.score, r.ncand = ids[off:off + m], sc[off:off + m], nc[off:off + m]
-                    off += m
-                lo = hi
+            sq = self.s_q[self._rr]
+            self._rr = (self._rr + 1) % len(self.s_q)
+            with torch.cuda.stream(sq):
+                if not ins:
+                    ev0.record()
+                if self._ins_done is not None:
+                    sq.wait_event(self._ins_done)
+                Q = self._pinned([r.points for r in qs])
+                qk = self._hash(Q)
+                self.stats.points_hashed += Q.shape[0]
+                bq, bs = self.base[:self.n], None if self.scale is None else self.scale[:self.n]
+                lo = 0
+                while lo < len(qs):     # one call per watermark group
+                    hi = lo
+                    while hi < len(qs) and qs[hi].watermark == qs[lo].watermark:
+                        hi += 1
+                    a = sum(r.points.shape[0] for r in qs[:lo])
+                    z = a + sum(r.points.shape[0] for r in qs[lo:hi])
+                    segs = [sg for sg in self.segments if sg.id_base < qs[lo].watermark]
+                    held.extend(segs)
+                    ids, sc, nc = lsh.lsh_query([sg.index for sg in segs], bq, Q[a:z],
+                                                qk[:, a:z], k=self.k,
+                                                watermark=qs[lo].watermark, metric=self.metric,
+                                                base_scale=bs)
+                    off = 0
+                    for r in qs[lo:hi]:
+                        m = r.points.shape[0]
+                        r.ids, r.score, r.ncand = ids[off:off + m], sc[off:off + m], nc[off:off + m]
+                        off += m
+                    lo = hi
+                ev1.record()
+        else:
+            with torch.cuda.stream(self.s_ins):
+                ev1.record()
+        return _Inflight(batch, nbytes, ev0, ev1, held, checks)
 
     # --------------------------------------------------------------- serve
     def serve(self, requests: list[Request], realtime: bool = True) -> Stats:
         """Serve the stream.  realtime=False admits every request at once in
         arrival order (the same batches as an infinitely fast arrival)."""
-        dev = self.base.device
         # watermarks follow arrival order (inserts before a query are visible)
         seen = self.arrived_inserts
         for r in requests:
@@ -189,62 +318,88 @@ class Server:
                 r.watermark = seen
         self.arrived_inserts = seen
 
-        def pinned(arrs: list) -> torch.Tensor:
-            # the requests' points copied once, into one pinned buffer (the
-            # host allocator keeps it until the copy to the device is done)
-            m = sum(a.shape[0] for a in arrs)
-            host = torch.empty((m, self.d), dtype=torch.float32, pin_memory=True)
-            off = 0
-            for a in arrs:
-                host[off:off + a.shape[0]].copy_(torch.from_numpy(a))
-                off += a.shape[0]
-            return host.to(dev, non_blocking=True)
-
-        inflight: deque = deque()
-        live = 0      # bytes of the batches in flight
+        inflight: list[_Inflight] = []
+        finished: list[_Inflight] = []
+        # a batch grows to at most its share of the budget, so that several
+        # batches can be in flight at once (a single larger request still
+        # runs, once the bytes in flight leave room for it)
+        slot = max(1, self.budget // self.max_inflight)
+        live = 0      # transient bytes of the batches in flight
         i = 0
+        t_ref = torch.cuda.Event(enable_timing=True)
+        t_ref.record(torch.cuda.default_stream(self.device))
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if realtime else (lambda: math.inf)
         stamp = lambda: time.perf_counter() - t0
+        self.stats.peak_resident_bytes = max(self.stats.peak_resident_bytes,
+                                             self.resident_bytes())
         while i < len(requests) or inflight:
-            while inflight and inflight[0][1].query():
-                ev0, ev1, reqs, nbytes = inflight.popleft()
+            for rec in [b for b in inflight if b.ev_end.query()]:
                 now = stamp()
-                for r in reqs:
+                for r in rec.reqs:
                     r.done = now
-                live -= nbytes
-                self.stats.busy_s += ev0.elapsed_time(ev1) * 1e-3
+                live -= rec.nbytes
+                self._verify(rec.checks)
+                rec.held = []
+                inflight.remove(rec)
+                finished.append(rec)
             now = clock()
+            admitted = False
             if (i < len(requests) and len(inflight) < self.max_inflight
                     and requests[i].arrival <= now):
-                batch, nbytes = [], 0
+                batch, nbytes, m_ins = [], 0, 0
                 while i < len(requests) and requests[i].arrival <= now:
-                    rb = self._request_bytes(requests[i])
-                    if batch and nbytes + rb > self.budget:
+                    r = requests[i]
+                    rb = self._request_bytes(r)
+                    mi = m_ins + (r.points.shape[0] if r.kind == "insert" else 0)
+                    tot = nbytes + rb + self._merge_bytes(mi) - self._merge_bytes(m_ins)
+                    if batch and (tot > slot or live + tot > self.budget):
                         break
-                    batch.append(requests[i])
-                    nbytes += rb
+                    if not batch and inflight and live + tot > self.budget:
+                        break
+                    batch.append(r)
+                    nbytes, m_ins = tot, mi
                     i += 1
-                for r in batch:
-                    r.batch = self.stats.batches
-                self.stats.batches += 1
-                self.stats.batch_sizes.append(sum(r.points.shape[0] for r in batch))
-                ev0 = torch.cuda.Event(enable_timing=True)
-                ev1 = torch.cuda.Event(enable_timing=True)
-                ev0.record()
-                self._run_batch(batch, pinned)
-                ev1.record()
-                live += nbytes
-                self.stats.peak_bytes = max(self.stats.peak_bytes, live)
-                inflight.append((ev0, ev1, batch, nbytes))
+                if batch:
+                    for r in batch:
+                        r.batch = self.stats.batches
+                    self.stats.batches += 1
+                    self.stats.batch_sizes.append(sum(r.points.shape[0] for r in batch))
+                    inflight.append(self._run_batch(batch, nbytes))
+                    live += nbytes
+                    self.stats.peak_bytes = max(self.stats.peak_bytes, live)
+                    self.stats.max_inflight_seen = max(self.stats.max_inflight_seen,
+                                                       len(inflight))
+                    self.stats.peak_resident_bytes = max(self.stats.peak_resident_bytes,
+                                                         self.resident_bytes())
+                    admitted = True
+            if admitted:
                 continue
             if inflight:
-                inflight[0][1].synchronize() if not realtime else time.sleep(20e-6)
+                if realtime:
+                    time.sleep(20e-6)
+                else:
+                    inflight[0].ev_end.synchronize()
             elif i < len(requests):
                 wait = requests[i].arrival - clock()
                 if wait > 0:
                     time.sleep(min(wait, 1e-3))
-        torch.cuda.synchronize()
+        torch.cuda.synchronize(self.device)
+        # device time: union and sum of the batches' [start, end] intervals
+        iv = sorted((t_ref.elapsed_time(b.ev_start) * 1e-3, t_ref.elapsed_time(b.ev_end) * 1e-3)
+                    for b in finished)
+        union, cur_lo, cur_hi = 0.0, None, None
+        for lo, hi in iv:
+            self.stats.batch_time_s += hi - lo
+            if cur_hi is None or lo > cur_hi:
+                if cur_hi is not None:
+                    union += cur_hi - cur_lo
+                cur_lo, cur_hi = lo, hi
+            else:
+                cur_hi = max(cur_hi, hi)
+        if cur_hi is not None:
+            union += cur_hi - cur_lo
+        self.stats.busy_s += union
         return self.stats
 
 
@@ -268,5 +423,10 @@ def summarize(requests: list[Request], stats: Stats, wall_s: float) -> dict:
         "points_per_s": round((qpts + ipts) / wall_s, 1),
         "batches": stats.batches, "mean_batch_points": round(float(np.mean(stats.batch_sizes)), 1),
         "segment_merges": stats.merges, "peak_budget_bytes": stats.peak_bytes,
-        "gpu_busy_frac": round(stats.busy_s / wall_s, 3),   # batch time / wall time
+        "peak_resident_bytes": stats.peak_resident_bytes,
+        "max_batches_in_flight": stats.max_inflight_seen,
+        "gpu_busy_frac": round(stats.busy_s / wall_s, 3),   # device-busy union / wall time
+        # summed batch device time over the busy union: above 1 when batches overlap
+        "device_overlap": round(stats.batch_time_s / stats.busy_s, 3) if stats.busy_s else None,
+        "builds_checked": stats.builds_checked,
     }

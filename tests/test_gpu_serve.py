@@ -23,20 +23,36 @@ def _setup(n0, d, K, L, w, family, seed):
 
 
 def _serve(n0=3000, d=64, K=8, L=8, w=8.0, family=lsh.E2LSH, n_req=60, max_points=40,
-           budget=60_000, seed=71, inflight=2, realtime=False):
+           budget=60_000, seed=71, inflight=2, realtime=False, storage="f32"):
     dev()
     x0, h, s, b, qsrc, isrc = _setup(n0, d, K, L, w, family, seed)
     reqs = serve.poisson_stream(n_req, 1e4, 0.7, max_points, d, qsrc, isrc, seed)
     srv = serve.Server(to_dev(x0), to_dev(h), to_dev(s), to_dev(b), K=K, L=L, w=w,
                        capacity=n0 + sum(r.points.shape[0] for r in reqs), budget_bytes=budget,
-                       k=10, metric=family, max_inflight=inflight, recheck=True)
+                       k=10, metric=family, max_inflight=inflight, recheck=True, storage=storage)
     stats = srv.serve(reqs, realtime=realtime)
-    return srv, reqs, stats, (x0, h, s, b, K, L, w, family)
+    return srv, reqs, stats, (x0, h, s, b, K, L, w, family, storage)
+
+
+def _oracle_points(srv, reqs, params):
+    """Every point in id order as the FP64 oracle sees it: FP32 values, or the
+    oracle's own BF16 / FP8 quantisation decoded (the GPU's stored codes must
+    equal the oracle's bit for bit)."""
+    x0, storage = params[0], params[8]
+    allx = np.concatenate([x0] + [r.points for r in reqs if r.kind == "insert"])
+    if storage == "f32":
+        return allx.astype(np.float64)
+    q, sc = oracle.quantise_rows(allx, storage)
+    n = allx.shape[0]
+    qg = to_host(srv.base[:n], np.uint16 if storage == "bf16" else np.uint8)
+    assert (qg == q).all(), "stored codes differ from the oracle's quantisation"
+    assert (to_host(srv.scale[:n]) == sc).all()
+    return oracle.decode(q, sc)
 
 
 def _check_oracle(srv, reqs, params):
-    x0, h, s, b, K, L, w, family = params
-    allx = np.concatenate([x0] + [r.points for r in reqs if r.kind == "insert"]).astype(np.float64)
+    x0, h, s, b, K, L, w, family, storage = params
+    allx = _oracle_points(srv, reqs, params)
     okw = dict(kind="cs", w=w, b=b, h=h, s=s)
     ref_idx = oracle.build_index(oracle.hash_points(allx, family, K, L, **okw)["keys"])
     for r in reqs:
@@ -55,9 +71,10 @@ def _check_oracle(srv, reqs, params):
             assert set(ids[i][strict]) == set(rids[i][strict])
 
 
-def test_serve_matches_oracle_and_alone():
-    srv, reqs, stats, params = _serve()
-    assert stats.batches > 3
+@pytest.mark.parametrize("storage", ["f32", "bf16", "fp8"])
+def test_serve_matches_oracle_and_alone(storage):
+    srv, reqs, stats, params = _serve(storage=storage)
+    assert stats.batches > 3 and stats.builds_checked >= 2
     _check_oracle(srv, reqs, params)
     # the same query alone (its own call, same watermark) gives the same bits
     segs = [sg.index for sg in srv.segments]
@@ -67,21 +84,44 @@ def test_serve_matches_oracle_and_alone():
         Q = to_dev(r.points)
         qk = srv._hash(Q)
         ids, sc, nc = lsh.lsh_query(segs, srv.base[:srv.n], Q, qk, k=10,
-                                    watermark=r.watermark, metric=srv.metric)
+                                    watermark=r.watermark, metric=srv.metric,
+                                    base_scale=None if srv.scale is None else srv.scale[:srv.n])
         assert (to_host(ids) == to_host(r.ids)).all()
         assert (to_host(sc).view(np.uint32) == to_host(r.score).view(np.uint32)).all()
         assert (to_host(nc) == to_host(r.ncand)).all()
 
 
-def test_serve_merges_segments_and_keeps_budget():
-    # a budget below most requests: every request runs alone, so inserts
-    # create more than 16 segments and force merges
-    srv, reqs, stats, params = _serve(n_req=90, budget=1, family=lsh.SRP, w=1.0, seed=73)
+def test_serve_merges_segments_and_runs_oversized_requests_alone():
+    # a budget below every request: each request runs alone, with nothing
+    # else in flight, so inserts create more than 16 segments and force merges
+    srv, reqs, stats, params = _serve(n_req=90, budget=1, family=lsh.SRP, w=1.0, seed=73,
+                                      inflight=4)
     assert stats.batches == len(reqs)
+    assert stats.max_inflight_seen == 1
     assert stats.merges >= 1 and len(srv.segments) <= serve.MAX_SEGMENTS
-    largest = max(srv._request_bytes(r) for r in reqs)
-    assert stats.peak_bytes <= 2 * largest
     _check_oracle(srv, reqs, params)
+
+
+@pytest.mark.parametrize("storage", ["f32", "fp8"])
+def test_serve_budget_bounds_bytes_in_flight(storage):
+    """With every request within the budget, the transient bytes of the
+    batches in flight never exceed it, while several batches are in flight
+    at once (their work overlaps on the device)."""
+    dev()
+    d, K, L, w, seed = 64, 8, 8, 8.0, 75
+    x0, h, s, b, qsrc, isrc = _setup(3000, d, K, L, w, lsh.E2LSH, seed)
+    reqs = serve.poisson_stream(120, 1e4, 0.7, 40, d, qsrc, isrc, seed)
+    probe = serve.Server(to_dev(x0), to_dev(h), to_dev(s), to_dev(b), K=K, L=L, w=w,
+                         capacity=4000, budget_bytes=1, storage=storage)
+    largest = max(probe._request_bytes(r) for r in reqs)
+    budget = 3 * largest
+    srv = serve.Server(to_dev(x0), to_dev(h), to_dev(s), to_dev(b), K=K, L=L, w=w,
+                       capacity=3000 + sum(r.points.shape[0] for r in reqs), budget_bytes=budget,
+                       k=10, max_inflight=4, recheck=True, storage=storage)
+    stats = srv.serve(reqs, realtime=False)
+    assert 0 < stats.peak_bytes <= budget
+    assert stats.max_inflight_seen >= 2
+    _check_oracle(srv, reqs, (x0, h, s, b, K, L, w, lsh.E2LSH, storage))
 
 
 def test_serve_realtime_latency_fields():

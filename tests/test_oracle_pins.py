@@ -652,3 +652,87 @@ def test_bf16_and_scale_decode(orc):
     x = orc.decode(bits, sc)
     want = v.to(torch.float64).numpy() * sc.astype(np.float64)[:, None]
     assert (x == want).all()
+
+
+# ---------------------------------------------------------------------------
+# low-precision storage (quantisation)
+# ---------------------------------------------------------------------------
+
+def _quant_edge_rows():
+    """Rows whose scale is 1 (max |x| = 1 for BF16, 448 for FP8) so their
+    quotients are the values themselves: exact halfway cases, values that
+    round to zero, signed zeros, the clamp, and a zero row."""
+    bf = np.zeros((3, 12), np.float32)
+    # BF16 steps are 2^-8 in [0.5, 1) and 2^-9 in [0.25, 0.5): 0.5 + 2^-9 is
+    # halfway between 0.5 and 0.5 + 2^-8 (ties to even: 0.5), 0.5 + 3*2^-9
+    # halfway between 0.5 + 2^-8 and 0.5 + 2^-7 (even: 0.5 + 2^-7),
+    # 0.25 + 2^-10 halfway between 0.25 and 0.25 + 2^-9 (even: 0.25)
+    bf[0, :8] = [1.0, 0.5 + 2 ** -9, 0.5 + 3 * 2 ** -9, -(0.5 + 2 ** -9), 0.25 + 2 ** -10, -0.0,
+                 2 ** -140, 0.75]
+    bf[1, :4] = [-1.0, 0.1, -0.3, 1e-30]
+    # bf[2] is a zero row: scale 1, every code zero
+    f8 = np.zeros((3, 12), np.float32)
+    # E4M3FN near 1: step 1/8; 1 + 1/16 is halfway (even: 1.0), 1 + 3/16 (even: 1.25);
+    # subnormal grid 2^-9: 2^-10 halfway between 0 and 2^-9 (even: 0), 3 * 2^-10 (even: 2^-8)
+    f8[0, :10] = [448.0, 1 + 1 / 16, 1 + 3 / 16, -(1 + 1 / 16), 2 ** -10, 3 * 2 ** -10, -0.0,
+                  -2 ** -11, 416.0, 432.0]
+    f8[1, :4] = [-448.0, 300.0, 2 ** -6, 17.0]
+    return bf, f8
+
+
+def test_quantise_matches_library_casts(orc):
+    """The oracle's exhaustive nearest-code search equals torch's
+    round-to-nearest-even casts (BF16, FP8-E4M3FN) applied to the binary32
+    quotients, on cluster data, sparse rows and the hand-made edge rows."""
+    from paper_2503_06737_amd import synth
+    bf, f8 = _quant_edge_rows()
+    data = [synth.gaussian_clusters(200, 300, 5, 0.1, 93), synth.sparse_uniform(100, 333, 0.2, 94),
+            (synth.gaussian_clusters(50, 64, 3, 1.0, 95) * 1e-4).astype(np.float32)]
+    for kind, edge in (("bf16", bf), ("fp8", f8)):
+        for x in data + [edge]:
+            q, sc = orc.quantise_rows(x, kind)
+            qt, sct = synth.quantise_rows(x, kind)
+            assert (sc.view(np.uint32) == sct.view(np.uint32)).all(), kind
+            assert (q == qt).all(), (kind, np.argwhere(q != qt)[:4])
+
+
+def test_quantise_hand_cases(orc):
+    """Hand-worked codes of the edge rows (ties to even, sign of zero, clamp)."""
+    bf, f8 = _quant_edge_rows()
+    q, sc = orc.quantise_rows(bf, "bf16")
+    assert sc.tolist() == [1.0, 1.0, 1.0]
+    assert q[0, :8].tolist() == [0x3F80, 0x3F00, 0x3F02, 0xBF00, 0x3E80, 0x8000, 0x0000, 0x3F40]
+    assert (q[2] == 0).all()
+    q, sc = orc.quantise_rows(f8, "fp8")
+    assert sc.tolist() == [1.0, 1.0, 1.0]
+    # 448 = 0x7E; 1.0 = 0x38; 1.25 = 0x3A; 2^-10 -> 0; 3*2^-10 -> 2^-8 = code 2;
+    # -0 -> 0x80; -2^-11 -> negative zero; 416 = 1.625*2^8 = 0x7D; 432 is halfway
+    # between 416 (odd mantissa 5) and 448 (even mantissa 6): 448
+    assert q[0, :10].tolist() == [0x7E, 0x38, 0x3A, 0xB8, 0x00, 0x02, 0x80, 0x80, 0x7D, 0x7E]
+    # -448 = 0xFE; 2^-6 is the smallest normal, 0x08; 17 is halfway between
+    # 16 = 0x58 (even) and 18 = 0x59: 16
+    assert q[1, :4].tolist() == [0xFE, orc_fp8_code(300.0), 0x08, 0x58]
+
+
+def orc_fp8_code(v):
+    """Code of the E4M3FN value nearest to v > 0 by a plain scan of the
+    decoded values (ties cannot occur for the values used here)."""
+    import oracle
+    vals = [(abs(oracle.fp8_value(c) - v), c) for c in range(0x7F)]
+    return min(vals)[1]
+
+
+def test_quantise_decode_error_bound(orc):
+    """Decoded values lie within half a code step of x: BF16 |err| <= 2^-9 |x|,
+    FP8 normals |err| <= 2^-4 |x|, subnormals <= 2^-10 * scale."""
+    from paper_2503_06737_amd import synth
+    x = synth.gaussian_clusters(300, 256, 5, 0.2, 96)
+    for kind in ("bf16", "fp8"):
+        q, sc = orc.quantise_rows(x, kind)
+        xd = orc.decode(q, sc)
+        err = np.abs(xd - x.astype(np.float64))
+        if kind == "bf16":
+            bound = np.abs(x) * 2.0 ** -8 + 1e-38
+        else:
+            bound = np.maximum(np.abs(x) * 2.0 ** -4, 2.0 ** -10 * sc[:, None]) * (1 + 1e-6)
+        assert (err <= bound).all(), kind
