@@ -11,10 +11,13 @@ Printed as one JSON line.  Beside the headline value the same run measures
 the dense E2LSH baseline (Y = X R on FP32 matrix cores, same index build),
 CS-SRP and dense SRP, query latency (p50/p99 of hash + probe + re-rank of
 query batches against the built index), the serving loop under sustained and
-overloaded request streams, CS against HCS at 500k x 4096, BF16/FP8 hashing
-with and without the FP64 recheck, per-kernel timings with HIP events on the
-stream the kernels run on, and the FP64 CPU oracle on the same workload (all
-rows hashed and one index built on the host cores).
+overloaded request streams with an FP32 base and sustained streams with a
+BF16 / FP8 base, CS against HCS at 500k x 4096, BF16/FP8 hashing with and
+without the FP64 recheck, per-kernel timings with HIP events on the stream
+the kernels run on, and the oracle leg: the FP64 CPU oracle on the same
+workload (all rows hashed and one index built on the host cores, all
+threads and one thread), then the low-precision servers' first answers
+checked against the oracle.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
@@ -255,6 +258,12 @@ def main():
     # ---------------------------------------------------------------- CPU oracle
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(x_host, h, s, b, K, L, w)
+        serving_x = res.get("extras", {}).get("serving")
+        for smp in SERVED_SAMPLES:
+            serving_x[smp["run"]]["oracle_agreement"] = oracle_agreement(smp)
+            print(f"[bench] {smp['run']} oracle agreement "
+                  f"{serving_x[smp['run']]['oracle_agreement']}", file=sys.stderr, flush=True)
+    SERVED_SAMPLES.clear()
     print(json.dumps(res), flush=True)
 
 
@@ -268,7 +277,6 @@ def query_latency(torch, lsh, synth, dev):
     print(f"[bench] serving-shaped data {xh.shape} in {time.time() - t0:.1f}s", file=sys.stderr,
           flush=True)
     X = torch.from_numpy(xh).to(dev)
-    del xh
     Q = torch.from_numpy(Qh).to(dev)
     hd = torch.from_numpy(h.view(np.int32)).to(dev)
     sd = torch.from_numpy(s).to(dev)
@@ -294,12 +302,20 @@ def query_latency(torch, lsh, synth, dev):
     lat = {"workload": wl.name, "k": 10, "batches": out}
     del idx, keys
     torch.cuda.empty_cache()
-    return lat, serving(torch, synth, dev, wl, X, hd, sd, bd)
+    return lat, serving(torch, synth, dev, wl, X, xh, hd, sd, bd)
 
 
-def serving(torch, synth, dev, wl, X, hd, sd, bd):
+# served answers kept for the oracle leg (agreement of the low-precision path)
+SERVED_SAMPLES = []
+
+
+def serving(torch, synth, dev, wl, X, xh, hd, sd, bd):
     """Continuously batched query/insert stream against the same index: a
-    sustainable Poisson rate and the planned 50,000 req/s (overload)."""
+    sustainable Poisson rate and the planned 50,000 req/s (overload) with an
+    FP32 base, then the sustainable rate with the base stored as BF16 and as
+    FP8-E4M3FN (per-row scales, FP64 near-edge recheck).  The answers of the
+    low-precision runs' first queries are kept for the oracle leg, which
+    compares them with the FP64 oracle on the same stored values."""
     from paper_2503_06737_amd import serve
     qpool = wl.points(400_000, stream=1)
     ipool = wl.points(100_000, stream=2)
@@ -312,33 +328,49 @@ def serving(torch, synth, dev, wl, X, hd, sd, bd):
             return pool[lo:lo + m]
         return take
 
-    def server(reqs):
+    def server(reqs, storage="f32"):
         cap = X.shape[0] + sum(r.points.shape[0] for r in reqs if r.kind == "insert")
         return serve.Server(X, hd, sd, bd, K=wl.K, L=wl.L, w=wl.w, capacity=cap,
-                            budget_bytes=2 << 30, k=10)
+                            budget_bytes=2 << 30, k=10, max_inflight=4, storage=storage,
+                            recheck=storage != "f32")
 
-    out = {}
-    for name, rate, n_req in (("sustained", 600.0, 1200), ("planned_overload", 50_000.0, 800)):
+    out = {"budget_bytes": 2 << 30, "max_inflight": 4, "query_streams": 2}
+    runs = (("sustained", 600.0, 1200, "f32"), ("planned_overload", 50_000.0, 20_000, "f32"),
+            ("sustained_bf16", 600.0, 1200, "bf16"), ("sustained_fp8", 600.0, 1200, "fp8"))
+    for name, rate, n_req, storage in runs:
         # warm-up, not measured: a server of the same configuration serves a
         # short stream of its own (device and pinned-memory allocator caches,
         # kernel set-up); the measured server then starts from that state
-        wreqs = serve.poisson_stream(n_req // 4, rate, 0.9, 4096, wl.d, src(qpool, "q"),
-                                     src(ipool, "i"), wl.seed + 4)
-        wsrv = server(wreqs)
+        wreqs = serve.poisson_stream(min(n_req // 4, 600), rate, 0.9, 4096, wl.d,
+                                     src(qpool, "q"), src(ipool, "i"), wl.seed + 4)
+        wsrv = server(wreqs, storage)
         wsrv.serve(wreqs, realtime=True)
         del wsrv
         reqs = serve.poisson_stream(n_req, rate, 0.9, 4096, wl.d, src(qpool, "q"),
                                     src(ipool, "i"), wl.seed + 3)
-        srv = server(reqs)
+        srv = server(reqs, storage)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = srv.serve(reqs, realtime=True)
         wall = time.perf_counter() - t0
         summ = serve.summarize(reqs, st, wall)
-        summ.update({"offered_req_per_s": rate, "query_frac": 0.9, "max_points": 4096})
+        summ.update({"offered_req_per_s": rate, "query_frac": 0.9, "max_points": 4096,
+                     "storage": storage, "recheck": storage != "f32",
+                     "resident_base_bytes": srv.base.numel() * srv.base.element_size()})
         out[name] = summ
         print(f"[bench] serving {name}: {summ}", file=sys.stderr, flush=True)
-        del srv
+        if storage != "f32":
+            # the first 64 query requests, with every insert before the last of them
+            qs = [r for r in reqs if r.kind == "query"][:64]
+            last = qs[-1].watermark
+            ins = [r.points for r in reqs if r.kind == "insert" and r.first_id < last]
+            SERVED_SAMPLES.append({
+                "run": name, "storage": storage, "base": xh, "inserts": ins,
+                "h": hd.cpu().numpy().view(np.uint32), "s": sd.cpu().numpy(),
+                "b": bd.cpu().numpy(), "K": wl.K, "L": wl.L, "w": wl.w,
+                "queries": [(r.points, r.watermark, r.ids.cpu().numpy(), r.score.cpu().numpy(),
+                             r.ncand.cpu().numpy()) for r in qs]})
+        del srv, reqs
         torch.cuda.empty_cache()
     out["workload"] = wl.name + " base, fresh query (stream 1) and insert (stream 2) draws"
     return out
@@ -465,27 +497,99 @@ def precision_path(torch, lsh, dev):
     return res
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x_host, h, s, b, K, L, w):
-    """The FP64 oracle (C, OpenMP) on this host over the same workload: every
-    row hashed (decode, CS sketch, discretise, keys; in row chunks to bound
-    memory) and one index over all keys (per-table sort)."""
+    """Oracle leg, part 1: the FP64 oracle (C, OpenMP) on this host over the
+    same workload, every row hashed (decode, CS sketch, discretise, keys; in
+    row chunks to bound memory) and one index over all keys (per-table sort).
+    Median of 3 after one warm-up, with all OpenMP threads; then once more
+    with one thread on the first 100,000 rows (scaled to points/s)."""
     import oracle
     oracle.lib()
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.max_threads()
+
+    def run(x):
+        n = x.shape[0]
+        keys = np.empty((L, n), np.uint64)
+        chunk = 50000
+        t0 = time.perf_counter()
+        for lo in range(0, n, chunk):
+            x64 = oracle.decode(x[lo:lo + chunk])
+            out = oracle.hash_points(x64, oracle.E2LSH, K, L, kind="cs", w=w, b=b, h=h, s=s)
+            keys[:, lo:lo + chunk] = out["keys"]
+        t_hash = time.perf_counter() - t0
+        oracle.build_index(keys)
+        return t_hash, time.perf_counter() - t0
+
     n = x_host.shape[0]
-    keys = np.empty((L, n), np.uint64)
-    chunk = 50000
-    t0 = time.perf_counter()
-    for lo in range(0, n, chunk):
-        x64 = oracle.decode(x_host[lo:lo + chunk])
-        out = oracle.hash_points(x64, oracle.E2LSH, K, L, kind="cs", w=w, b=b, h=h, s=s)
-        keys[:, lo:lo + chunk] = out["keys"]
-    t_hash = time.perf_counter() - t0
-    oracle.build_index(keys)
-    spent = time.perf_counter() - t0
+    run(x_host[:100_000])                         # warm-up
+    times = sorted((run(x_host) for _ in range(3)), key=lambda t: t[1])
+    t_hash, spent = times[1]
+    oracle.set_threads(1)
+    n1 = min(n, 100_000)
+    t1_hash, t1 = run(x_host[:n1])
+    oracle.set_threads(threads)
     return {"value": round(n / spent, 1), "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"the whole workload ({n} rows): FP64 hashing {t_hash:.1f}s + one index "
-                      f"build over all keys {spent - t_hash:.1f}s"}
+            "sample": f"the whole workload ({n} rows), median of 3: FP64 hashing {t_hash:.2f}s + "
+                      f"one index build over all keys {spent - t_hash:.2f}s",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread": {"value": round(n1 / t1, 1), "unit": "points/s", "cores": 1,
+                              "sample": f"first {n1} rows: hashing {t1_hash:.2f}s + index "
+                                        f"{t1 - t1_hash:.2f}s"}}
+
+
+def oracle_agreement(smp):
+    """Oracle leg, part 2: the answers a low-precision server gave, against
+    the FP64 oracle over the same stored values.  The oracle quantises the
+    base and the inserts itself (its codes equal the device's bit for bit, as
+    the tests check), decodes them to FP64, hashes and indexes them, and
+    answers every sampled query at its watermark.  candidates_equal: the
+    query's candidate count equals the oracle's (the union of its buckets);
+    topk_equal: the top-k ids equal the oracle's outside near-ties of score."""
+    import oracle
+    t0 = time.perf_counter()
+    allx = np.concatenate([smp["base"]] + smp["inserts"]) if smp["inserts"] else smp["base"]
+    q, sc = oracle.quantise_rows(allx, smp["storage"])
+    del allx
+    n = q.shape[0]
+    K, L, w = smp["K"], smp["L"], smp["w"]
+    okw = dict(kind="cs", w=w, b=smp["b"], h=smp["h"], s=smp["s"])
+    x64 = np.empty((n, q.shape[1]), np.float64)
+    keys = np.empty((L, n), np.uint64)
+    chunk = 100_000
+    for lo in range(0, n, chunk):
+        x64[lo:lo + chunk] = oracle.decode(q[lo:lo + chunk], sc[lo:lo + chunk])
+        keys[:, lo:lo + chunk] = oracle.hash_points(x64[lo:lo + chunk], oracle.E2LSH, K, L,
+                                                    **okw)["keys"]
+    del q
+    idx = oracle.build_index(keys)
+    del keys
+    npts = cand_eq = topk_eq = 0
+    for pts, wm, ids, score, ncand in smp["queries"]:
+        q64 = pts.astype(np.float64)
+        qk = oracle.hash_points(q64, oracle.E2LSH, K, L, **okw)["keys"]
+        rids, rsc, rnc = oracle.query([idx], x64, q64, qk, 10, wm, oracle.E2LSH)
+        npts += q64.shape[0]
+        cand_eq += int((ncand == rnc).sum())
+        for i in range(q64.shape[0]):
+            fin = np.isfinite(rsc[i])
+            kth = rsc[i][fin][-1] if fin.any() else np.inf
+            strict = rsc[i] < kth * (1 - 1e-5) - 1e-5
+            topk_eq += int(set(ids[i][strict]) == set(rids[i][strict]))
+    return {"query_requests": len(smp["queries"]), "query_points": npts,
+            "candidates_equal_frac": round(cand_eq / max(npts, 1), 6),
+            "topk_equal_frac": round(topk_eq / max(npts, 1), 6),
+            "oracle_points": n, "oracle_s": round(time.perf_counter() - t0, 1)}
 
 
 if __name__ == "__main__":

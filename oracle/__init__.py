@@ -55,6 +55,8 @@ def _declare(L):
     L.orc_assign_components.argtypes = [vp, i64, i32, vp, vp]
     L.orc_keys_e2lsh.argtypes = [vp, i64, i32, i32, i32, vp]
     L.orc_keys_srp.argtypes = [vp, i64, i32, i32, i32, vp]
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_max_threads.restype = C.c_int
     L.orc_mix64.argtypes = [C.c_uint64]
     L.orc_mix64.restype = C.c_uint64
     L.orc_fp8_e4m3fn_value.argtypes = [C.c_uint8]
@@ -98,6 +100,15 @@ def quantise_rows(x: np.ndarray, kind: str):
     sc = np.empty(n, np.float32)
     lib().orc_quantise_rows(_p(x), n, d, dt, _p(q), _p(sc))
     return q, sc
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads the oracle's loops use from now on."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def fp8_value(bits: int) -> float:

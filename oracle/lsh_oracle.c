@@ -29,6 +29,7 @@
  * rounded separately, exactly as written.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -110,25 +111,41 @@ static uint16_t nearest_bf16(float v)
     return (lo & 1) ? hi : lo;
 }
 
-/* Nearest E4M3FN pattern by search over every finite non-negative code
- * (0x00..0x7e); the sign bit is that of v. */
+/* Nearest E4M3FN pattern.  The finite non-negative codes 0x00..0x7e decode
+ * to increasing values, so a bisection over their decoded values finds the
+ * last code c with value(c) <= |v|; the nearer of c and c + 1 wins, a tie
+ * going to the code with an even last bit.  The sign bit is that of v. */
+static double g_e4m3_vals[0x7f];
+
+static void fill_e4m3_vals(void)
+{
+    for (int c = 0; c <= 0x7e; ++c)
+        g_e4m3_vals[c] = orc_fp8_e4m3fn_value((uint8_t)c);
+}
+
 static uint8_t nearest_e4m3fn(float v)
 {
     double a = fabs((double)v);
-    int best = 0;
-    double bd = INFINITY;
-    for (int c = 0; c <= 0x7e; ++c) {
-        double dd = fabs(orc_fp8_e4m3fn_value((uint8_t)c) - a);
-        if (dd < bd || (dd == bd && (c & 1) == 0 && (best & 1) == 1)) {
-            bd = dd;
-            best = c;
-        }
+    int lo = 0, hi = 0x7e; /* invariant: value(lo) <= a (value(0) = 0) */
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (g_e4m3_vals[mid] <= a)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    int best = lo;
+    if (lo < 0x7e) {
+        double dlo = a - g_e4m3_vals[lo], dhi = g_e4m3_vals[lo + 1] - a;
+        if (dhi < dlo || (dhi == dlo && (lo & 1)))
+            best = lo + 1;
     }
     return (uint8_t)((signbit(v) ? 0x80 : 0) | best);
 }
 
 void orc_quantise_rows(const float *x, int64_t n, int32_t d, int dtype, void *q, float *scale)
 {
+    fill_e4m3_vals();
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         const float *xr = x + i * (int64_t)d;
@@ -553,3 +570,8 @@ int64_t orc_query_one(int32_t nseg, const int64_t *seg_n, int32_t L,
     free(c);
     return nu;
 }
+
+/* Threads of the OpenMP loops above (for timing the oracle at a given count). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -96,6 +96,9 @@ class Stats:
     max_inflight_seen: int = 0
     builds_checked: int = 0
     batch_sizes: list = field(default_factory=list)
+    # batches whose host-side enqueue took over 2 ms:
+    # (batch, points, insert points, merged, enqueue ms)
+    slow_enqueues: list = field(default_factory=list)
 
 
 @dataclass
@@ -365,7 +368,14 @@ class Server:
                         r.batch = self.stats.batches
                     self.stats.batches += 1
                     self.stats.batch_sizes.append(sum(r.points.shape[0] for r in batch))
+                    te = time.perf_counter()
+                    merges = self.stats.merges
                     inflight.append(self._run_batch(batch, nbytes))
+                    te = (time.perf_counter() - te) * 1e3
+                    if te > 2.0:
+                        self.stats.slow_enqueues.append(
+                            (self.stats.batches - 1, self.stats.batch_sizes[-1], m_ins,
+                             self.stats.merges > merges, round(te, 2)))
                     live += nbytes
                     self.stats.peak_bytes = max(self.stats.peak_bytes, live)
                     self.stats.max_inflight_seen = max(self.stats.max_inflight_seen,
@@ -429,4 +439,6 @@ def summarize(requests: list[Request], stats: Stats, wall_s: float) -> dict:
         # summed batch device time over the busy union: above 1 when batches overlap
         "device_overlap": round(stats.batch_time_s / stats.busy_s, 3) if stats.busy_s else None,
         "builds_checked": stats.builds_checked,
+        "slow_enqueues": len(stats.slow_enqueues),
+        "slowest_enqueues": sorted(stats.slow_enqueues, key=lambda e: -e[4])[:5],
     }
