@@ -195,6 +195,35 @@ lsh_status lsh_hash_hcs(const lsh_points *pts, int32_t N, const int32_t *d_k, co
                         const uint32_t *h_k, const int8_t *s_k, const lsh_disc *disc,
                         const lsh_out *out, void *workspace, size_t ws_bytes, void *stream);
 
+/* Independent tables (the protocol of Section 6: L hash tables, each built
+ * from a sketch of its own with K components).  Table t has its own count
+ * sketch y^t_r = sum over j with h_t(j) = r of s_t(j) x_j, r < K (Definition
+ * def_cs with m = K), discretised as floor((sqrt(K) y^t_r + b[tK + r]) / w)
+ * (Definition CS_Eucl_LSH at m = K) or [y^t_r > 0] (Definition
+ * cs_consine_lsh); its K codes form its key as for lsh_hash_cs.  Each point
+ * costs O(L d) additions against O(d) for lsh_hash_cs.
+ *   h: [L][d] bins in [0, K) (table t at h[t*d + j]); s: [L][d] signs.
+ *   disc: m = K * L, b[m] with table t's shifts at [tK, tK + K); comp_slot
+ *   must be NULL; recheck is ignored: the sums are exact 64-bit fixed point
+ *   (error below 2^-62 * d * max|x| per term) and discretised in FP64, so
+ *   codes equal the FP64 evaluation except within that error of an edge.
+ *   out: as for lsh_hash_cs (codes/proj at position tK + r).
+ * Limits: L <= 64; the state takes about d * L bytes of LDS plus up to
+ * 1024 * K + 2048 bytes per wave, at most 160 KB in all (EINVAL
+ * beyond).  Any dtype. */
+lsh_status lsh_hash_cs_tables(const lsh_points *pts, const uint32_t *h, const int8_t *s,
+                              const lsh_disc *disc, const lsh_out *out, void *stream);
+
+/* HCS variant of lsh_hash_cs_tables (Definitions HCS_Eucl_LSH and
+ * hcs_consine_lsh with one higher-order sketch per table): table t reads the
+ * point as the tensor d_1 x ... x d_N (first mode fastest, zero-padded) and
+ * sketches it with its own per-mode hashes h_{t,k}: [d_k] -> [m_k] and signs.
+ *   prod m_k must equal K.  h_k, s_k: [L][sum d_k], table t's N mode tables
+ *   back to back at offset t * sum d_k.  Other arguments as above. */
+lsh_status lsh_hash_hcs_tables(const lsh_points *pts, int32_t N, const int32_t *d_k,
+                               const int32_t *m_k, const uint32_t *h_k, const int8_t *s_k,
+                               const lsh_disc *disc, const lsh_out *out, void *stream);
+
 /* Dense E2LSH / SRP (Section 3.1): y = x R on FP32 matrix cores, then
  * floor((y + b)/w) (no sqrt(m) scale) or sgn(y).  R: [d][m] row-major FP32.
  * F32 points only; recheck must be 0 and comp_slot NULL (permute the

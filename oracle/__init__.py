@@ -262,6 +262,37 @@ def hash_points(x: np.ndarray, family: int, K: int, L: int, *, kind: str, w: flo
 # step 5: index
 # ----------------------------------------------------------------------------
 
+def hash_points_tables(x: np.ndarray, family: int, K: int, L: int, *, kind: str,
+                       w: float = 1.0, b: np.ndarray | None = None, h=None, s=None, dk=None,
+                       mk=None, hk=None, sk=None) -> dict:
+    """Independent tables, the protocol of Section 6: table t has a sketch of
+    its own with K components (kind "cs": h[t], s[t] over the d coordinates;
+    kind "hcs": per-mode tables hk[t][k], sk[t][k] with prod mk = K),
+    discretised with scale sqrt(K) (the sketch length, Definition
+    CS_Eucl_LSH) and shifts b[tK:(t+1)K]; its K codes form its key.
+
+    Returns y [n][K L] (table t at columns tK..tK+K-1), codes, near, keys [L][n].
+    """
+    x = np.ascontiguousarray(x, np.float64)
+    ys = []
+    for t in range(L):
+        if kind == "cs":
+            ys.append(cs_sketch(x, h[t], s[t], K))
+        elif kind == "hcs":
+            assert int(np.prod(mk)) == K
+            ys.append(hcs_sketch(x, dk, mk, hk[t], sk[t]))
+        else:
+            raise ValueError(kind)
+    y = np.ascontiguousarray(np.concatenate(ys, axis=1))
+    if family == E2LSH:
+        codes, near = disc_e2lsh(y, b, w, math.sqrt(K))
+        keys = keys_e2lsh(codes, K, L)
+    else:
+        codes, near = disc_srp(y, row_norms(x))
+        keys = keys_srp(codes, K, L)
+    return {"y": y, "codes": codes, "near": near, "keys": keys}
+
+
 def build_index(keys: np.ndarray, id_base: int = 0) -> dict:
     keys = np.ascontiguousarray(keys, np.uint64)
     L, n = keys.shape

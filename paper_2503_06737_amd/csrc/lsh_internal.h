@@ -42,6 +42,7 @@ int device_cu_count();
 
 // Argument checks shared by the entry points (set the error message).
 lsh_status check_points(const lsh_points *p);
+lsh_status check_disc(const lsh_disc *c);
 
 // -------------------------------------------------------------- device side
 

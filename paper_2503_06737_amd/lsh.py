@@ -22,7 +22,7 @@ E2LSH, SRP = 0, 1
 F32, BF16, FP8 = 0, 1, 2
 STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ENOMEM", -3: "LSH_EHIP", -5: "LSH_ERANGE"}
 
-EXPORTS = ("lsh_quantize_rows", "lsh_build_check_async", "lsh_hash_workspace_bytes", "lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense",
+EXPORTS = ("lsh_hash_cs_tables", "lsh_hash_hcs_tables", "lsh_quantize_rows", "lsh_build_check_async", "lsh_hash_workspace_bytes", "lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense",
            "lsh_index_bytes", "lsh_build_workspace_bytes", "lsh_build_index",
            "lsh_index_get_view", "lsh_index_free", "lsh_query", "lsh_last_error", "lsh_version")
 
@@ -73,6 +73,8 @@ def lib() -> C.CDLL:
         L.lsh_hash_cs_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lsh_hash_hcs.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.lsh_hash_dense.argtypes = [vp, vp, vp, vp, vp]
+        L.lsh_hash_cs_tables.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lsh_hash_hcs_tables.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.lsh_index_bytes.argtypes = [i64, i32]
         L.lsh_index_bytes.restype = sz
         L.lsh_build_workspace_bytes.argtypes = [i64, i32]
@@ -87,7 +89,8 @@ def lib() -> C.CDLL:
         L.lsh_query.argtypes = [vp, i32, vp, vp, vp, i64, i32, i64, i32, vp, vp, vp, vp]
         L.lsh_last_error.restype = C.c_char_p
         L.lsh_version.restype = i32
-        for fn in ("lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense", "lsh_build_index",
+        for fn in ("lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_cs_tables",
+                   "lsh_hash_hcs_tables", "lsh_hash_dense", "lsh_build_index",
                    "lsh_index_get_view", "lsh_query", "lsh_build_check", "lsh_build_check_async",
                    "lsh_quantize_rows"):
             getattr(L, fn).restype = i32
@@ -207,6 +210,34 @@ def lsh_hash_hcs(x, dk, mk, hk, sk, *, family, K, L, w=1.0, b=None, scale=None, 
     disc = _disc(family, K, L, w, b, recheck, comp_slot)
     _check(lib().lsh_hash_hcs(C.byref(pts), N, dka, mka, _ptr(hk), _ptr(sk), C.byref(disc),
                               C.byref(out), _ptr(ws), wsb, _stream()))
+    return o
+
+
+def lsh_hash_cs_tables(x, h, s, *, family, K, L, w=1.0, b=None, scale=None, keys=True,
+                       codes=False, proj=False, counters=None):
+    """Independent per-table count sketches: h, s are [L][d] device tensors
+    (table t's bins in [0, K) and signs).  Returns the dict of lsh_hash_cs."""
+    pts = points(x, scale)
+    o, out = _outputs(x.shape[0], K * L, L, x.device, keys, codes, proj, counters)
+    disc = _disc(family, K, L, w, b, 0)
+    _check(lib().lsh_hash_cs_tables(C.byref(pts), _ptr(h), _ptr(s), C.byref(disc), C.byref(out),
+                                    _stream()))
+    return o
+
+
+def lsh_hash_hcs_tables(x, dk, mk, hk, sk, *, family, K, L, w=1.0, b=None, scale=None,
+                        keys=True, codes=False, proj=False, counters=None):
+    """Independent per-table higher-order count sketches: hk, sk are
+    [L][sum dk] device tensors (table t's per-mode tables back to back)."""
+    pts = points(x, scale)
+    assert math.prod(mk) == K
+    o, out = _outputs(x.shape[0], K * L, L, x.device, keys, codes, proj, counters)
+    N = len(dk)
+    dka = (C.c_int32 * N)(*dk)
+    mka = (C.c_int32 * N)(*mk)
+    disc = _disc(family, K, L, w, b, 0)
+    _check(lib().lsh_hash_hcs_tables(C.byref(pts), N, dka, mka, _ptr(hk), _ptr(sk),
+                                     C.byref(disc), C.byref(out), _stream()))
     return o
 
 

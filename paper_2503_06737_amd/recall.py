@@ -11,11 +11,13 @@ for the E2LSH families, 1 - cos for SRP).  Every hash, index and query call
 is the library's.
 
 Two ways of forming the L tables are measured:
-  shared     one sketch of m = K·L components per point, table t owning
-             components [tK, (t+1)K) (this library's design: O(d) work per
-             point for all tables together);
-  per_table  L independent sketches of m = K components, one per table (the
-             experiments' protocol: O(L·d) work per point).
+  shared     one sketch of m = K·L components per point, split into the L
+             tables (this library's design: O(d) work per point for all
+             tables together); HCS components are assigned to tables by a
+             seeded permutation;
+  per_table  L independent sketches of K components, one per table (the
+             experiments' protocol: O(L·d) work per point), hashed in one
+             pass over the points by lsh_hash_cs_tables / lsh_hash_hcs_tables.
 
 It also reports the bytes of each family's projection state (the space
 comparison of Section 6): dense m·d FP32 weights, CS d bins + d signs, HCS
@@ -39,37 +41,70 @@ FAMILIES = ("dense", "cs", "hcs2", "hcs3")
 
 
 def hcs_modes(d: int, m: int, N: int):
-    """Mode sizes for HCS of order N = 2 or 3 and m a multiple of 8: d_k with
-    product >= d (near-equal powers of two), m_k with product m: (8, m/8) or
-    (2, 4, m/8) (for m = 8: (2, 4) or (2, 2, 2))."""
+    """Mode sizes for HCS of order N = 2 or 3, m a power of two: d_k are
+    near-equal powers of two with product >= d, and the factors of 2 of m
+    go one by one to the mode with the most indices per bin, so the smallest
+    d_k / m_k is as large as the totals allow."""
     e = math.ceil(math.log2(d))
     base, extra = divmod(e, N)
-    dk = [1 << (base + (1 if i < extra else 0)) for i in range(N)]
-    if m == 8:
-        mk = [2, 4] if N == 2 else [2, 2, 2]
-    else:
-        mk = [8, m // 8] if N == 2 else [2, 4, m // 8]
+    ed = [base + (1 if i < extra else 0) for i in range(N)]
+    em = int(round(math.log2(m)))
+    assert (1 << em) == m, "m must be a power of two"
+    ek = [0] * N
+    for _ in range(em):   # each factor 2 of m to the mode with the most indices per bin
+        i = max(range(N), key=lambda k: (ed[k] - ek[k], -ek[k]))
+        ek[i] += 1
+    dk, mk = [1 << x for x in ed], [1 << x for x in ek]
     assert N in (2, 3) and math.prod(mk) == m and math.prod(dk) >= d
     return dk, mk
 
 
-def hasher(fam: str, metric: int, d: int, K: int, L: int, w: float, seed: int, dev: str):
-    """A function hashing rows with a fresh, device-resident hash state."""
+def hash_state(fam: str, protocol: str, d: int, K: int, L: int, w: float, seed: int) -> dict:
+    """The random state of one repetition, as host arrays (the same arrays the
+    oracle takes).  shared: one sketch of m = K L components (a seeded
+    permutation assigns the HCS components to tables, so that no table sits
+    inside one mode slice); per_table: L independent sketches of K."""
     m = K * L
-    b = torch.from_numpy(synth.shifts(m, w, seed)).to(dev) if metric == lsh.E2LSH else None
-    if fam == "dense":
-        R = torch.from_numpy(synth.gaussian_matrix(d, m, seed)).to(dev)
-        return lambda A: lsh.lsh_hash_dense(A, R, family=metric, K=K, L=L, w=w, b=b)
-    if fam == "cs":
-        h, s = synth.cs_state(d, m, seed)
-        hd = torch.from_numpy(h.view(np.int32)).to(dev)
-        sd = torch.from_numpy(s).to(dev)
-        return lambda A: lsh.lsh_hash_cs(A, hd, sd, family=metric, K=K, L=L, w=w, b=b)
-    dk, mk = hcs_modes(d, m, 2 if fam == "hcs2" else 3)
-    hk, sk = synth.hcs_state(dk, mk, seed)
-    hkd = torch.from_numpy(np.concatenate(hk).view(np.int32)).to(dev)
-    skd = torch.from_numpy(np.concatenate(sk)).to(dev)
-    return lambda A: lsh.lsh_hash_hcs(A, dk, mk, hkd, skd, family=metric, K=K, L=L, w=w, b=b)
+    st = {"fam": fam, "protocol": protocol, "K": K, "L": L, "w": w,
+          "b": synth.shifts(m, w, seed)}
+    if fam == "dense":  # independent columns: L tables of K columns are L dense tables
+        st["R"] = synth.gaussian_matrix(d, m, seed)
+    elif protocol == "shared" and fam == "cs":
+        st["h"], st["s"] = synth.cs_state(d, m, seed)
+    elif protocol == "shared":
+        st["dk"], st["mk"] = hcs_modes(d, m, 2 if fam == "hcs2" else 3)
+        hk, sk = synth.hcs_state(st["dk"], st["mk"], seed)
+        st["hk"], st["sk"] = np.concatenate(hk), np.concatenate(sk)
+        st["slot"] = synth.component_slots(m, seed)
+    elif fam == "cs":
+        st["h"], st["s"] = synth.cs_tables_state(d, K, L, seed)
+    else:
+        st["dk"], st["mk"] = hcs_modes(d, K, 2 if fam == "hcs2" else 3)
+        st["hk"], st["sk"] = synth.hcs_tables_state(st["dk"], st["mk"], L, seed)
+    return st
+
+
+def table_keys(st: dict, metric: int, dev: str):
+    """A function returning the [L][rows] keys of a point set under state st
+    (device-resident copies of the state, every hash a library call)."""
+    K, L, w = st["K"], st["L"], st["w"]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(
+        a.view(np.int32) if a.dtype == np.uint32 else a)).to(dev)
+    b = t(st["b"]) if metric == lsh.E2LSH else None
+    kw = dict(family=metric, K=K, L=L, w=w, b=b)
+    if st["fam"] == "dense":
+        R = t(st["R"])
+        return lambda A: lsh.lsh_hash_dense(A, R, **kw)["keys"]
+    if st["fam"] == "cs":
+        h, s = t(st["h"]), t(st["s"])
+        if st["protocol"] == "shared":
+            return lambda A: lsh.lsh_hash_cs(A, h, s, **kw)["keys"]
+        return lambda A: lsh.lsh_hash_cs_tables(A, h, s, **kw)["keys"]
+    hk, sk, dk, mk = t(st["hk"]), t(st["sk"]), st["dk"], st["mk"]
+    if st["protocol"] == "shared":
+        slot = t(st["slot"])
+        return lambda A: lsh.lsh_hash_hcs(A, dk, mk, hk, sk, comp_slot=slot, **kw)["keys"]
+    return lambda A: lsh.lsh_hash_hcs_tables(A, dk, mk, hk, sk, **kw)["keys"]
 
 
 def exact_topk(X: torch.Tensor, Q: torch.Tensor, k: int, metric: int) -> torch.Tensor:
@@ -83,15 +118,6 @@ def exact_topk(X: torch.Tensor, Q: torch.Tensor, k: int, metric: int) -> torch.T
     # a stable sort keeps equal scores in id order: (score, id) order
     order = torch.argsort(s, dim=1, stable=True)
     return order[:, :k]
-
-
-def table_keys(fam, metric, d, K, L, w, seed, dev, protocol):
-    """A function returning the [L][rows] keys of a point set."""
-    if protocol == "shared":
-        h = hasher(fam, metric, d, K, L, w, seed, dev)
-        return lambda A: h(A)["keys"]
-    hs = [hasher(fam, metric, d, K, 1, w, seed + 100003 * t, dev) for t in range(L)]
-    return lambda A: torch.cat([h(A)["keys"] for h in hs], dim=0)
 
 
 def run(nq: int = 100, reps: int = 20, Ls=(1, 2, 4, 8, 16, 32, 50), k: int = 50, K: int = 8,
@@ -111,8 +137,8 @@ def run(nq: int = 100, reps: int = 20, Ls=(1, 2, 4, 8, 16, 32, 50), k: int = 50,
                 for L in Ls:
                     rec, qt, cand = [], [], []
                     for r in range(reps):
-                        keys_of = table_keys(fam, metric, d, K, L, w, 7000 + 97 * r + L, dev,
-                                             protocol)
+                        st = hash_state(fam, protocol, d, K, L, w, 7000 + 97 * r + L)
+                        keys_of = table_keys(st, metric, dev)
                         idx = lsh.lsh_build_index(keys_of(X))
                         torch.cuda.synchronize()
                         t0 = time.perf_counter()

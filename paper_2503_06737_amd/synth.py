@@ -115,6 +115,28 @@ def hcs_state(dk, mk, seed: int):
     return hk, sk
 
 
+def cs_tables_state(d: int, K: int, L: int, seed: int):
+    """Independent per-table count-sketch state: h [L][d] uniform in [0, K),
+    s [L][d] in {+1, -1} (one draw per table from its own stream)."""
+    h = np.empty((L, d), np.uint32)
+    s = np.empty((L, d), np.int8)
+    for t in range(L):
+        h[t], s[t] = cs_state(d, K, seed * 1000 + t)
+    return h, s
+
+
+def hcs_tables_state(dk, mk, L: int, seed: int):
+    """Independent per-table HCS state: for each table its per-mode hashes and
+    signs, laid out as [L][sum d_k] (table t's N mode tables back to back)."""
+    tot = int(sum(dk))
+    h = np.empty((L, tot), np.uint32)
+    s = np.empty((L, tot), np.int8)
+    for t in range(L):
+        hk, sk = hcs_state(dk, mk, seed * 1000 + t)
+        h[t], s[t] = np.concatenate(hk), np.concatenate(sk)
+    return h, s
+
+
 def component_slots(m: int, seed: int) -> np.ndarray:
     """A uniformly random permutation of range(m): code position of each sketch
     component (which components form which table)."""

@@ -736,3 +736,89 @@ def test_quantise_decode_error_bound(orc):
         else:
             bound = np.maximum(np.abs(x) * 2.0 ** -4, 2.0 ** -10 * sc[:, None]) * (1 + 1e-6)
         assert (err <= bound).all(), kind
+
+
+# ---------------------------------------------------------------------------
+# independent per-table sketches (the protocol of Section 6)
+# ---------------------------------------------------------------------------
+
+def test_tables_worked_example(orc):
+    """Hand-worked: two tables of K = 2 bins, scale sqrt(K) = sqrt(2), table t
+    using shifts b[2t], b[2t+1] (tests/golden/tables_worked_example.json)."""
+    g = json.load(open(os.path.join(GOLD, "tables_worked_example.json")))
+    x = np.array([g["x"]])
+    h = np.array(g["h"], np.uint32)
+    s = np.array(g["s"], np.int8)
+    b = np.array(g["b"], np.float32)
+    out = orc.hash_points_tables(x, orc.E2LSH, g["K"], g["L"], kind="cs", w=g["w"], b=b, h=h, s=s)
+    assert out["y"][0].tolist() == g["y"]
+    assert out["codes"][0].tolist() == g["codes"]
+    bits = orc.hash_points_tables(x, orc.SRP, g["K"], g["L"], kind="cs", h=h, s=s)
+    assert bits["codes"][0].tolist() == g["srp_bits"]
+    assert bits["keys"][:, 0].tolist() == [0b11, 0b00]
+
+
+def test_tables_one_table_is_the_shared_sketch(orc):
+    """Special case: with L = 1 the single table's sketch is the shared sketch
+    of m = K components (same h, s, b, scale sqrt(K) = sqrt(m))."""
+    gr = np.random.default_rng(101)
+    x = gr.standard_normal((40, 37))
+    K = 8
+    h, s = gr.integers(0, K, 37).astype(np.uint32), gr.choice([-1, 1], 37).astype(np.int8)
+    b = (gr.random(K) * 4).astype(np.float32)
+    for fam in (orc.E2LSH, orc.SRP):
+        a = orc.hash_points_tables(x, fam, K, 1, kind="cs", w=4.0, b=b, h=h[None], s=s[None])
+        c = orc.hash_points(x, fam, K, 1, kind="cs", w=4.0, b=b, h=h, s=s)
+        assert (a["codes"] == c["codes"]).all() and (a["keys"] == c["keys"]).all()
+
+
+def test_tables_are_independent_and_ordered(orc):
+    """Invariant: table t depends on its own state and shifts only.  Changing
+    table u's hashes leaves every other table's sketch and key unchanged, and
+    permuting the tables (state and shift blocks together) permutes the keys;
+    a wrong table offset or shift block fails this."""
+    gr = np.random.default_rng(102)
+    n, d, K, L = 30, 50, 4, 5
+    x = gr.standard_normal((n, d))
+    h = gr.integers(0, K, (L, d)).astype(np.uint32)
+    s = gr.choice([-1, 1], (L, d)).astype(np.int8)
+    b = (gr.random(K * L) * 2).astype(np.float32)
+    base = orc.hash_points_tables(x, orc.E2LSH, K, L, kind="cs", w=2.0, b=b, h=h, s=s)
+    h2 = h.copy()
+    h2[3] = gr.integers(0, K, d)
+    alt = orc.hash_points_tables(x, orc.E2LSH, K, L, kind="cs", w=2.0, b=b, h=h2, s=s)
+    keep = [t for t in range(L) if t != 3]
+    assert (alt["keys"][keep] == base["keys"][keep]).all()
+    assert (alt["y"][:, 12:16] != base["y"][:, 12:16]).any()
+    perm = np.array([2, 0, 4, 1, 3])
+    bp = b.reshape(L, K)[perm].reshape(-1)
+    pr = orc.hash_points_tables(x, orc.E2LSH, K, L, kind="cs", w=2.0, b=bp, h=h[perm], s=s[perm])
+    # table t of the permuted set is table perm[t] of the original, but its
+    # key is seeded with its own index t: compare the codes, not the keys
+    for t in range(L):
+        assert (pr["codes"][:, t * K:(t + 1) * K] ==
+                base["codes"][:, perm[t] * K:(perm[t] + 1) * K]).all()
+
+
+def test_tables_hcs_is_cs_under_each_tables_composite_hash(orc):
+    """Per-table HCS equals per-table CS when each table's composite bin and
+    sign (first mode fastest) are given as its CS state."""
+    gr = np.random.default_rng(103)
+    dk, mk, L = (4, 3, 5), (2, 2, 2), 3
+    d = 4 * 3 * 5
+    K = 8
+    x = gr.standard_normal((25, d))
+    hk = [[gr.integers(0, m, dd).astype(np.uint32) for dd, m in zip(dk, mk)] for _ in range(L)]
+    sk = [[gr.choice([-1, 1], dd).astype(np.int8) for dd in dk] for _ in range(L)]
+    hc = np.zeros((L, d), np.uint32)
+    sc = np.zeros((L, d), np.int8)
+    for t in range(L):
+        for j in range(d):
+            i1, i2, i3 = j % 4, (j // 4) % 3, j // 12
+            hc[t, j] = hk[t][0][i1] + 2 * (hk[t][1][i2] + 2 * hk[t][2][i3])
+            sc[t, j] = sk[t][0][i1] * sk[t][1][i2] * sk[t][2][i3]
+    b = (gr.random(K * L) * 4).astype(np.float32)
+    a = orc.hash_points_tables(x, orc.E2LSH, K, L, kind="hcs", w=4.0, b=b, dk=dk, mk=mk, hk=hk, sk=sk)
+    c = orc.hash_points_tables(x, orc.E2LSH, K, L, kind="cs", w=4.0, b=b, h=hc, s=sc)
+    np.testing.assert_allclose(a["y"], c["y"], rtol=0, atol=1e-12)
+    assert (a["keys"] == c["keys"]).all()
