@@ -36,6 +36,7 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hash_kernel_c2_traffic.json")
 HASH_SRC = os.path.join(ROOT, "paper_2503_06737_amd", "csrc", "hash.hip")
 FP32_MFMA_PEAK_TF = 157.3    # MI355X dense FP32 matrix, TFLOP/s
+BF16_MFMA_PEAK_TF = 2500.0   # MI355X dense BF16 matrix, TFLOP/s
 
 
 def _events(torch):
@@ -235,6 +236,11 @@ def main():
                 "hash_only": round(extra["dense_e2lsh"]["hash_ms"] / hash_med, 2),
                 "hash_plus_index": round(extra["dense_e2lsh"]["ms_per_step"] /
                                          float(np.median(step_ms)), 2)}
+            extra["dense_e2lsh_bf16"] = dense_bf16_step(torch, lsh, X, keys, build, n, d, K, L,
+                                                        m, w, R, bd, args.steps)
+            extra["speedup_cs_vs_dense_e2lsh"]["hash_only_vs_bf16_dense"] = round(
+                extra["dense_e2lsh_bf16"]["hash_ms"] / hash_med, 2)
+            extra["space"] = state_space(torch, lsh, synth, d, m, K, L, hd, sd, Rd)
 
         # query latency: hash + probe + exact re-rank of query batches against a
         # CS-E2LSH index of the serving-shaped workload (2M x 960 Gaussian
@@ -265,6 +271,63 @@ def main():
                   f"{serving_x[smp['run']]['oracle_agreement']}", file=sys.stderr, flush=True)
     SERVED_SAMPLES.clear()
     print(json.dumps(res), flush=True)
+
+
+def dense_bf16_step(torch, lsh, X, keys, build, n, d, K, L, m, w, R, bd, steps):
+    """Dense E2LSH with BF16 operands on the BF16 matrix cores (the points
+    stored as BF16 with row scales, R rounded to BF16), the same index
+    build: how fast a dense projection gets when its precision is given up.
+    The BF16 copy of the points is made on the device before timing."""
+    q, sc = lsh.lsh_quantize_rows(X, "bf16")
+    Rt = torch.from_numpy(R).to(X.device).to(torch.bfloat16).T.contiguous().view(torch.int16)
+
+    def hash_once():
+        keys.copy_(lsh.lsh_hash_dense_bf16(q, sc, Rt, family=0, K=K, L=L, w=w, b=bd)["keys"])
+
+    def hash_only():
+        return lsh.lsh_hash_dense_bf16(q, sc, Rt, family=0, K=K, L=L, w=w, b=bd)
+
+    def step():
+        hash_once()
+        build()
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    st_ms, _ = timed(torch, step, max(3, steps // 2))
+    hs_ms, _ = timed(torch, hash_only, max(3, steps // 2))
+    tf = 2.0 * n * d * m / (hs_ms * 1e-3) / 1e12
+    e = {"ms_per_step": round(st_ms, 4), "points_per_s": round(n / (st_ms * 1e-3), 1),
+         "hash_ms": round(hs_ms, 4), "hash_tflops": round(tf, 2),
+         "mfma_frac": round(tf / BF16_MFMA_PEAK_TF, 4), "dtype": "bf16 operands, f32 accumulate",
+         "note": "step time includes a key copy; hash_ms is the projection+discretise+key kernel"}
+    print(f"[bench] dense_e2lsh_bf16: {e}", file=sys.stderr, flush=True)
+    del q, sc, Rt
+    return e
+
+
+def state_space(torch, lsh, synth, d, m, K, L, hd, sd, Rd):
+    """Bytes of each family's projection state as allocated on the device
+    (the space comparison of Section 6): dense R (FP32 and BF16), the count
+    sketch's h and s, the higher-order sketch's per-mode tables for the
+    500k x 4096 workload's N = 2 and 3, and L independent per-table count
+    sketches (h and s per table)."""
+    res = {"d": d, "m": m,
+           "dense_f32": Rd.numel() * Rd.element_size(),
+           "dense_bf16": Rd.numel() * 2,
+           "cs": hd.numel() * hd.element_size() + sd.numel() * sd.element_size()}
+    wl3 = synth.C3
+    for i, name in enumerate(("hcs_n2", "hcs_n3")):
+        hk, sk = wl3.hcs_state(i)
+        hkd = torch.from_numpy(np.concatenate(hk).view(np.int32)).to(hd.device)
+        skd = torch.from_numpy(np.concatenate(sk)).to(hd.device)
+        res[name] = {"d": wl3.d, "dk": list(wl3.hcs[i][0]), "mk": list(wl3.hcs[i][1]),
+                     "bytes": hkd.numel() * 4 + skd.numel(), "cs_same_d_bytes": 5 * wl3.d}
+    ht, st = synth.cs_tables_state(d, K, L, 3)
+    htd, std_ = torch.from_numpy(ht.view(np.int32)).to(hd.device), torch.from_numpy(st).to(hd.device)
+    res["cs_per_table"] = htd.numel() * 4 + std_.numel()
+    print(f"[bench] space {res}", file=sys.stderr, flush=True)
+    return res
 
 
 def query_latency(torch, lsh, synth, dev):

@@ -231,6 +231,17 @@ lsh_status lsh_hash_hcs_tables(const lsh_points *pts, int32_t N, const int32_t *
 lsh_status lsh_hash_dense(const lsh_points *pts, const float *R, const lsh_disc *disc,
                           const lsh_out *out, void *stream);
 
+/* Dense E2LSH / SRP with BF16 operands on the BF16 matrix cores (FP32
+ * accumulation): the low-precision bound of the dense baseline.  Points are
+ * LSH_BF16 codes with row scales; Rt holds the projection vectors as rows,
+ * Rt[l*ldr + j] = r_l[j] (BF16 bits, ldr >= d), i.e. R transposed.  Then
+ * y_l = row_scale[i] * sum_j q_ij r_l[j] (FP32) is discretised as in
+ * lsh_hash_dense.  The FP32 sums of exact BF16 products deviate from the FP64
+ * evaluation by FP32 rounding over d terms.  recheck must be 0 and comp_slot
+ * NULL. */
+lsh_status lsh_hash_dense_bf16(const lsh_points *pts, const uint16_t *Rt, int64_t ldr,
+                               const lsh_disc *disc, const lsh_out *out, void *stream);
+
 /* ------------------------------------------------------------------ index */
 
 typedef struct lsh_index lsh_index; /* host-side descriptor; arrays live in caller memory */

@@ -22,7 +22,7 @@ E2LSH, SRP = 0, 1
 F32, BF16, FP8 = 0, 1, 2
 STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ENOMEM", -3: "LSH_EHIP", -5: "LSH_ERANGE"}
 
-EXPORTS = ("lsh_hash_cs_tables", "lsh_hash_hcs_tables", "lsh_quantize_rows", "lsh_build_check_async", "lsh_hash_workspace_bytes", "lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense",
+EXPORTS = ("lsh_hash_dense_bf16", "lsh_hash_cs_tables", "lsh_hash_hcs_tables", "lsh_quantize_rows", "lsh_build_check_async", "lsh_hash_workspace_bytes", "lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense",
            "lsh_index_bytes", "lsh_build_workspace_bytes", "lsh_build_index",
            "lsh_index_get_view", "lsh_index_free", "lsh_query", "lsh_last_error", "lsh_version")
 
@@ -74,6 +74,7 @@ def lib() -> C.CDLL:
         L.lsh_hash_hcs.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.lsh_hash_dense.argtypes = [vp, vp, vp, vp, vp]
         L.lsh_hash_cs_tables.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lsh_hash_dense_bf16.argtypes = [vp, vp, i64, vp, vp, vp]
         L.lsh_hash_hcs_tables.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.lsh_index_bytes.argtypes = [i64, i32]
         L.lsh_index_bytes.restype = sz
@@ -90,7 +91,7 @@ def lib() -> C.CDLL:
         L.lsh_last_error.restype = C.c_char_p
         L.lsh_version.restype = i32
         for fn in ("lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_cs_tables",
-                   "lsh_hash_hcs_tables", "lsh_hash_dense", "lsh_build_index",
+                   "lsh_hash_hcs_tables", "lsh_hash_dense_bf16", "lsh_hash_dense", "lsh_build_index",
                    "lsh_index_get_view", "lsh_query", "lsh_build_check", "lsh_build_check_async",
                    "lsh_quantize_rows"):
             getattr(L, fn).restype = i32
@@ -248,6 +249,19 @@ def lsh_hash_dense(x, R, *, family, K, L, w=1.0, b=None, keys=True, codes=False,
     o, out = _outputs(x.shape[0], m, L, x.device, keys, codes, proj, None)
     disc = _disc(family, K, L, w, b, 0)
     _check(lib().lsh_hash_dense(C.byref(pts), _ptr(R), C.byref(disc), C.byref(out), _stream()))
+    return o
+
+
+def lsh_hash_dense_bf16(x, scale, Rt, *, family, K, L, w=1.0, b=None, keys=True, codes=False,
+                        proj=False):
+    """Dense E2LSH / SRP with BF16 operands: x [n][d] BF16 bits (int16) with
+    float32 row scales, Rt [m][d] BF16 bits (row l = projection vector r_l)."""
+    pts = points(x, scale)
+    assert Rt.dim() == 2 and Rt.stride(1) == 1 and Rt.shape[0] == K * L
+    o, out = _outputs(x.shape[0], K * L, L, x.device, keys, codes, proj, None)
+    disc = _disc(family, K, L, w, b, 0)
+    _check(lib().lsh_hash_dense_bf16(C.byref(pts), _ptr(Rt), Rt.stride(0), C.byref(disc),
+                                     C.byref(out), _stream()))
     return o
 
 

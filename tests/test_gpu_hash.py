@@ -343,3 +343,28 @@ def test_invalid_hash_state_is_counted():
     lsh.lsh_hash_cs(to_dev(x), to_dev(h2), to_dev(s), family=1, K=K, L=L, counters=cnt,
                     comp_slot=to_dev(slot))
     assert to_host(cnt, np.uint64)[3] == (h2 == 5).sum()
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+@pytest.mark.parametrize("n,d,K,L", [(10000, 1024, 8, 16), (1003, 784, 16, 64), (333, 100, 5, 7)])
+def test_dense_bf16_parity(n, d, K, L, family):
+    """BF16 dense projection (BF16 points with row scales, BF16 R, FP32
+    accumulation on the BF16 matrix cores) against the FP64 oracle over the
+    same BF16 values: projections within the dense band (d-term FP32 sums),
+    codes equal outside the near-edge band."""
+    dev()
+    import torch
+    m = K * L
+    x = synth.gaussian_clusters(n, d, 20, 0.1, 440 + d)
+    q, sc = synth.quantise_rows(x, "bf16")
+    x64 = oracle.decode(q, sc)
+    R = synth.gaussian_matrix(d, m, 441)
+    Rb = torch.from_numpy(R).to(torch.bfloat16)
+    R16 = Rb.to(torch.float32).numpy()                  # the BF16 values, exactly
+    Rt = Rb.T.contiguous().view(torch.int16).to(dev())  # [m][d] bits
+    b = synth.shifts(m, 4.0, 442)
+    ref = oracle.hash_points(x64, family, K, L, kind="dense", w=4.0, b=b, R=R16)
+    out = lsh.lsh_hash_dense_bf16(to_dev(q), to_dev(sc), Rt, family=family, K=K, L=L, w=4.0,
+                                  b=to_dev(b) if family == 0 else None, codes=True, proj=True)
+    compare_hash(out, ref, x64, K, L, weight_max=float(np.abs(R16).max()),
+                 what=f"dense bf16 n={n} d={d}")
