@@ -241,6 +241,7 @@ def main():
             extra["speedup_cs_vs_dense_e2lsh"]["hash_only_vs_bf16_dense"] = round(
                 extra["dense_e2lsh_bf16"]["hash_ms"] / hash_med, 2)
             extra["space"] = state_space(torch, lsh, synth, d, m, K, L, hd, sd, Rd)
+            extra["per_table_sketches"] = tables_throughput(torch, lsh, synth, X, bd, hash_med)
 
         # query latency: hash + probe + exact re-rank of query batches against a
         # CS-E2LSH index of the serving-shaped workload (2M x 960 Gaussian
@@ -304,6 +305,50 @@ def dense_bf16_step(torch, lsh, X, keys, build, n, d, K, L, m, w, R, bd, steps):
     print(f"[bench] dense_e2lsh_bf16: {e}", file=sys.stderr, flush=True)
     del q, sc, Rt
     return e
+
+
+def tables_throughput(torch, lsh, synth, X, bd, shared_ms):
+    """Independent per-table sketches (the protocol of Section 6: L sketches
+    of K components, O(L d) additions per point) against the shared sketch
+    (one sketch of K L components, O(d)): on the image-like 1M x 784 points
+    at K = 16, L = 64, and on 10k x 1024 cluster points at the recall
+    protocol's K = 8, L = 16."""
+    res = {}
+    n, d = X.shape
+    K, L = 16, 64
+    ht, st = synth.cs_tables_state(d, K, L, 11)
+    htd = torch.from_numpy(ht.view(np.int32)).to(X.device)
+    std_ = torch.from_numpy(st).to(X.device)
+    fn = lambda: lsh.lsh_hash_cs_tables(X, htd, std_, family=0, K=K, L=L, w=4.0, b=bd)
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    ms, _ = timed(torch, fn, 5)
+    res["image_like_1M_784_K16_L64"] = {
+        "per_table_ms": round(ms, 3), "shared_ms": round(shared_ms, 4),
+        "per_table_points_per_s": round(n / (ms * 1e-3), 1),
+        "ratio": round(ms / shared_ms, 1), "additions_ratio": L}
+    wl = synth.C1
+    Xc = torch.from_numpy(wl.points()).to(X.device)
+    K, L = 8, 16
+    ht, st = synth.cs_tables_state(wl.d, K, L, 12)
+    hs, ss = synth.cs_state(wl.d, K * L, 12)
+    b = torch.from_numpy(synth.shifts(K * L, 4.0, 12)).to(X.device)
+    t = lambda a: torch.from_numpy(a.view(np.int32) if a.dtype == np.uint32 else a).to(X.device)
+    htd, std_, hsd, ssd = t(ht), t(st), t(hs), t(ss)
+    ftab = lambda: lsh.lsh_hash_cs_tables(Xc, htd, std_, family=0, K=K, L=L, w=4.0, b=b)
+    fsh = lambda: lsh.lsh_hash_cs(Xc, hsd, ssd, family=0, K=K, L=L, w=4.0, b=b)
+    for f in (ftab, fsh):
+        for _ in range(2):
+            f()
+    torch.cuda.synchronize()
+    mt, _ = timed(torch, ftab, 10)
+    msh, _ = timed(torch, fsh, 10)
+    res["clusters_10k_1024_K8_L16"] = {
+        "per_table_ms": round(mt, 4), "shared_ms": round(msh, 4),
+        "ratio": round(mt / msh, 2), "additions_ratio": L}
+    print(f"[bench] per-table sketches {res}", file=sys.stderr, flush=True)
+    return res
 
 
 def state_space(torch, lsh, synth, d, m, K, L, hd, sd, Rd):
