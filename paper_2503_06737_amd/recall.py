@@ -41,20 +41,23 @@ FAMILIES = ("dense", "cs", "hcs2", "hcs3")
 
 
 def hcs_modes(d: int, m: int, N: int):
-    """Mode sizes for HCS of order N = 2 or 3, m a power of two: d_k are
-    near-equal powers of two with product >= d, and the factors of 2 of m
-    go one by one to the mode with the most indices per bin, so the smallest
+    """Mode sizes for HCS of order N = 2 or 3: d_k are near-equal powers of
+    two with product >= d, and the prime factors of m (largest first) go one
+    by one to the mode with the most indices per bin, so the smallest
     d_k / m_k is as large as the totals allow."""
     e = math.ceil(math.log2(d))
     base, extra = divmod(e, N)
-    ed = [base + (1 if i < extra else 0) for i in range(N)]
-    em = int(round(math.log2(m)))
-    assert (1 << em) == m, "m must be a power of two"
-    ek = [0] * N
-    for _ in range(em):   # each factor 2 of m to the mode with the most indices per bin
-        i = max(range(N), key=lambda k: (ed[k] - ek[k], -ek[k]))
-        ek[i] += 1
-    dk, mk = [1 << x for x in ed], [1 << x for x in ek]
+    dk = [1 << (base + (1 if i < extra else 0)) for i in range(N)]
+    primes, r, p = [], m, 2
+    while r > 1:
+        while r % p == 0:
+            primes.append(p)
+            r //= p
+        p += 1
+    mk = [1] * N
+    for f in sorted(primes, reverse=True):
+        i = max(range(N), key=lambda k: (dk[k] / mk[k], -mk[k]))
+        mk[i] *= f
     assert N in (2, 3) and math.prod(mk) == m and math.prod(dk) >= d
     return dk, mk
 

@@ -18,7 +18,8 @@ and insert requests arrive over time, and every kernel is a library call
   at once.  A request larger than the budget runs alone, once nothing else is
   in flight.  Resident bytes (the base and the segments'
   keys and indexes) are counted separately.
-* Streams.  Inserts run on one stream, in id order: the points are appended
+* Streams.  Inserts run on one stream, in id order (the streams are shared
+  by the servers of a device, so cached device memory carries over): the points are appended
   to the base, hashed, and indexed as a new segment whose ids continue from
   the last one.  Queries run on a pool of query streams; a batch's queries
   wait on an event recorded after the latest insert, so they see every point
@@ -40,6 +41,7 @@ and insert requests arrive over time, and every kernel is a library call
 """
 from __future__ import annotations
 
+import gc
 import math
 import time
 from dataclasses import dataclass, field
@@ -97,8 +99,9 @@ class Stats:
     builds_checked: int = 0
     batch_sizes: list = field(default_factory=list)
     # batches whose host-side enqueue took over 2 ms:
-    # (batch, points, insert points, merged, enqueue ms)
+    # (batch, points, insert points, merged, enqueue ms, of which pinned copies ms)
     slow_enqueues: list = field(default_factory=list)
+    gc_pauses_ms: list = field(default_factory=list)  # the collector's passes while serving
 
 
 @dataclass
@@ -130,6 +133,21 @@ def poisson_stream(n_req: int, rate: float, query_frac: float, max_points: int, 
     return out
 
 
+# Streams shared by every server on a device.  torch's caching allocator
+# keeps freed device blocks per stream, so a server that reuses the streams
+# of an earlier one (a warm-up run, a restarted service) reuses its cached
+# blocks instead of calling the runtime's allocator, which can synchronize
+# the device, in the middle of a stream.
+_STREAM_POOL: dict = {}
+
+
+def _streams(dev, nq: int):
+    key = (str(dev), nq)
+    if key not in _STREAM_POOL:
+        _STREAM_POOL[key] = (torch.cuda.Stream(dev), [torch.cuda.Stream(dev) for _ in range(nq)])
+    return _STREAM_POOL[key]
+
+
 class Server:
     def __init__(self, base: torch.Tensor, h, s, b, *, K: int, L: int, w: float, capacity: int,
                  budget_bytes: int, k: int = 10, metric: int = lsh.E2LSH, max_inflight: int = 4,
@@ -151,8 +169,7 @@ class Server:
         self.base = torch.empty((capacity, self.d), dtype=elt, device=dev)
         self.scale = (None if storage == "f32"
                       else torch.empty(capacity, dtype=torch.float32, device=dev))
-        self.s_ins = torch.cuda.Stream(dev)
-        self.s_q = [torch.cuda.Stream(dev) for _ in range(max(1, query_streams))]
+        self.s_ins, self.s_q = _streams(dev, max(1, query_streams))
         self._rr = 0
         self._ins_done: torch.cuda.Event | None = None
         n0 = base.shape[0]
@@ -261,10 +278,13 @@ class Server:
         ev1 = torch.cuda.Event(enable_timing=True)
         checks: list = []
         held: list = []
+        tp = 0.0  # host time spent copying request points into pinned memory
         if ins:
             with torch.cuda.stream(self.s_ins):
                 ev0.record()
+                t0 = time.perf_counter()
                 pts = self._pinned([r.points for r in ins])
+                tp += time.perf_counter() - t0
                 self._append(pts, checks)
                 done = torch.cuda.Event()
                 done.record()
@@ -278,7 +298,9 @@ class Server:
                     ev0.record()
                 if self._ins_done is not None:
                     sq.wait_event(self._ins_done)
+                t0 = time.perf_counter()
                 Q = self._pinned([r.points for r in qs])
+                tp += time.perf_counter() - t0
                 qk = self._hash(Q)
                 self.stats.points_hashed += Q.shape[0]
                 bq, bs = self.base[:self.n], None if self.scale is None else self.scale[:self.n]
@@ -305,6 +327,7 @@ class Server:
         else:
             with torch.cuda.stream(self.s_ins):
                 ev1.record()
+        self._last_pin_ms = tp * 1e3
         return _Inflight(batch, nbytes, ev0, ev1, held, checks)
 
     # --------------------------------------------------------------- serve
@@ -321,6 +344,27 @@ class Server:
                 r.watermark = seen
         self.arrived_inserts = seen
 
+        # The objects alive now (the request stream, the resident state) are
+        # moved out of the collector's reach: its full passes would otherwise
+        # walk them all and stall the request loop for tens of milliseconds.
+        gc.collect()
+        gc.freeze()
+        gc_t = {}
+
+        def gc_cb(phase, info):
+            if phase == "start":
+                gc_t["t"] = time.perf_counter()
+            elif "t" in gc_t:
+                self.stats.gc_pauses_ms.append(round((time.perf_counter() - gc_t.pop("t")) * 1e3, 3))
+
+        gc.callbacks.append(gc_cb)
+        try:
+            return self._serve(requests, realtime)
+        finally:
+            gc.callbacks.remove(gc_cb)
+            gc.unfreeze()
+
+    def _serve(self, requests: list[Request], realtime: bool) -> Stats:
         inflight: list[_Inflight] = []
         finished: list[_Inflight] = []
         # a batch grows to at most its share of the budget, so that several
@@ -375,7 +419,8 @@ class Server:
                     if te > 2.0:
                         self.stats.slow_enqueues.append(
                             (self.stats.batches - 1, self.stats.batch_sizes[-1], m_ins,
-                             self.stats.merges > merges, round(te, 2)))
+                             self.stats.merges > merges, round(te, 2),
+                             round(self._last_pin_ms, 2)))
                     live += nbytes
                     self.stats.peak_bytes = max(self.stats.peak_bytes, live)
                     self.stats.max_inflight_seen = max(self.stats.max_inflight_seen,
@@ -440,5 +485,7 @@ def summarize(requests: list[Request], stats: Stats, wall_s: float) -> dict:
         "device_overlap": round(stats.batch_time_s / stats.busy_s, 3) if stats.busy_s else None,
         "builds_checked": stats.builds_checked,
         "slow_enqueues": len(stats.slow_enqueues),
+        "gc_passes": len(stats.gc_pauses_ms),
+        "gc_pause_max_ms": max(stats.gc_pauses_ms) if stats.gc_pauses_ms else 0.0,
         "slowest_enqueues": sorted(stats.slow_enqueues, key=lambda e: -e[4])[:5],
     }
