@@ -37,7 +37,8 @@ and insert requests arrive over time, and every kernel is a library call
   count stops the server with `IndexBuildError`.
 * A request's latency runs from its arrival to the moment the host observes
   its batch's completion event, and includes the host-to-device copy of its
-  points (they arrive in host memory).
+  points (they arrive in host memory and pass through a fixed ring of pinned
+  chunks, allocated once per device).
 """
 from __future__ import annotations
 
@@ -99,9 +100,10 @@ class Stats:
     builds_checked: int = 0
     batch_sizes: list = field(default_factory=list)
     # batches whose host-side enqueue took over 2 ms:
-    # (batch, points, insert points, merged, enqueue ms, of which pinned copies ms)
+    # (batch, points, insert points, merged, enqueue ms, of which staging copies ms)
     slow_enqueues: list = field(default_factory=list)
     gc_pauses_ms: list = field(default_factory=list)  # the collector's passes while serving
+    staging_wait_s: float = 0.0   # host waits for a pinned staging chunk to come free
 
 
 @dataclass
@@ -148,6 +150,65 @@ def _streams(dev, nq: int):
     return _STREAM_POOL[key]
 
 
+class _PinnedRing:
+    """Fixed pinned host chunks that stage request points on their way to the
+    device.  A chunk is reused once the copy that read it has run (the event
+    recorded after that copy), so serving never allocates pinned memory: the
+    runtime's pinned allocation of a new, larger buffer took tens of
+    milliseconds on the request path.  Shared by the servers of a device."""
+
+    def __init__(self, nchunks: int, chunk_bytes: int):
+        self.bufs = [torch.empty(chunk_bytes, dtype=torch.uint8, pin_memory=True)
+                     for _ in range(nchunks)]
+        self.evs: list = [None] * nchunks
+        self.chunk_bytes = chunk_bytes
+        self.i = 0
+        self.wait_s = 0.0   # host time spent waiting for a chunk's copy to finish
+
+    def to_device(self, arrs: list, d: int, dev) -> torch.Tensor:
+        """The rows of arrs ([m_i][d] float32 host arrays), in order, as one
+        [sum m_i][d] device tensor written on the current stream."""
+        m = sum(a.shape[0] for a in arrs)
+        out = torch.empty((m, d), dtype=torch.float32, device=dev)
+        rows = self.chunk_bytes // (4 * d)
+        stream = torch.cuda.current_stream(dev)
+        o, ai, ar = 0, 0, 0
+        while o < m:
+            j = self.i
+            self.i = (j + 1) % len(self.bufs)
+            if self.evs[j] is not None:
+                t = time.perf_counter()
+                self.evs[j].synchronize()
+                self.wait_s += time.perf_counter() - t
+            host = self.bufs[j][:rows * d * 4].view(torch.float32).view(rows, d)
+            hn = host.numpy()
+            f = 0
+            while f < rows and ai < len(arrs):
+                t = min(rows - f, arrs[ai].shape[0] - ar)
+                hn[f:f + t] = arrs[ai][ar:ar + t]
+                f, ar = f + t, ar + t
+                if ar == arrs[ai].shape[0]:
+                    ai, ar = ai + 1, 0
+            out[o:o + f].copy_(host[:f], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            self.evs[j] = ev
+            o += f
+        return out
+
+
+_RING_POOL: dict = {}
+RING_CHUNKS, RING_CHUNK_BYTES = 64, 4 << 20
+
+
+def _ring(dev, d: int) -> _PinnedRing:
+    key = str(dev)
+    r = _RING_POOL.get(key)
+    if r is None or r.chunk_bytes < 4 * d:
+        r = _RING_POOL[key] = _PinnedRing(RING_CHUNKS, max(RING_CHUNK_BYTES, 4 * d))
+    return r
+
+
 class Server:
     def __init__(self, base: torch.Tensor, h, s, b, *, K: int, L: int, w: float, capacity: int,
                  budget_bytes: int, k: int = 10, metric: int = lsh.E2LSH, max_inflight: int = 4,
@@ -170,6 +231,7 @@ class Server:
         self.scale = (None if storage == "f32"
                       else torch.empty(capacity, dtype=torch.float32, device=dev))
         self.s_ins, self.s_q = _streams(dev, max(1, query_streams))
+        self.ring = _ring(dev, self.d)
         self._rr = 0
         self._ins_done: torch.cuda.Event | None = None
         n0 = base.shape[0]
@@ -260,16 +322,9 @@ class Server:
 
     # --------------------------------------------------------------- batch
     def _pinned(self, arrs: list) -> torch.Tensor:
-        """The requests' points copied once into one pinned buffer, then to
-        the device on the current stream (the host allocator keeps the
-        buffer until that copy is done)."""
-        m = sum(a.shape[0] for a in arrs)
-        host = torch.empty((m, self.d), dtype=torch.float32, pin_memory=True)
-        off = 0
-        for a in arrs:
-            host[off:off + a.shape[0]].copy_(torch.from_numpy(a))
-            off += a.shape[0]
-        return host.to(self.device, non_blocking=True)
+        """The requests' points staged through the pinned ring and copied to
+        the device on the current stream."""
+        return self.ring.to_device(arrs, self.d, self.device)
 
     def _run_batch(self, batch: list[Request], nbytes: int) -> _Inflight:
         ins = [r for r in batch if r.kind == "insert"]
@@ -296,13 +351,15 @@ class Server:
             with torch.cuda.stream(sq):
                 if not ins:
                     ev0.record()
-                if self._ins_done is not None:
-                    sq.wait_event(self._ins_done)
                 t0 = time.perf_counter()
                 Q = self._pinned([r.points for r in qs])
                 tp += time.perf_counter() - t0
                 qk = self._hash(Q)
                 self.stats.points_hashed += Q.shape[0]
+                # the bucket lookup sees every insert that arrived before
+                # (hashing the queries does not depend on them)
+                if self._ins_done is not None:
+                    sq.wait_event(self._ins_done)
                 bq, bs = self.base[:self.n], None if self.scale is None else self.scale[:self.n]
                 lo = 0
                 while lo < len(qs):     # one call per watermark group
@@ -371,6 +428,7 @@ class Server:
         # batches can be in flight at once (a single larger request still
         # runs, once the bytes in flight leave room for it)
         slot = max(1, self.budget // self.max_inflight)
+        wait0 = self.ring.wait_s
         live = 0      # transient bytes of the batches in flight
         i = 0
         t_ref = torch.cuda.Event(enable_timing=True)
@@ -440,6 +498,7 @@ class Server:
                 if wait > 0:
                     time.sleep(min(wait, 1e-3))
         torch.cuda.synchronize(self.device)
+        self.stats.staging_wait_s += self.ring.wait_s - wait0
         # device time: union and sum of the batches' [start, end] intervals
         iv = sorted((t_ref.elapsed_time(b.ev_start) * 1e-3, t_ref.elapsed_time(b.ev_end) * 1e-3)
                     for b in finished)
@@ -487,5 +546,6 @@ def summarize(requests: list[Request], stats: Stats, wall_s: float) -> dict:
         "slow_enqueues": len(stats.slow_enqueues),
         "gc_passes": len(stats.gc_pauses_ms),
         "gc_pause_max_ms": max(stats.gc_pauses_ms) if stats.gc_pauses_ms else 0.0,
+        "staging_wait_ms": round(stats.staging_wait_s * 1e3, 3),
         "slowest_enqueues": sorted(stats.slow_enqueues, key=lambda e: -e[4])[:5],
     }
