@@ -597,7 +597,8 @@ def precision_path(torch, lsh, dev):
             e["recheck" if rc else "fast"] = {
                 "ms": round(med, 4), "gbs": round(n * bytes_pp / (med * 1e-3) / 1e9, 1),
                 **({"recomputed": int(cnt[0]), "changed": int(cnt[1]),
-                    "changed_per_million_codes": round(cnt[1] / (n * K * L) * 1e6, 3)} if rc else {})}
+                    "changed_per_million_codes": round(cnt[1] / (n * K * L) * 1e6, 3)} if rc
+                   else {"uncertain": int(cnt[0])})}
         res[name] = e
         print(f"[bench] precision {name}: {e}", file=sys.stderr, flush=True)
         del q

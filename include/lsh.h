@@ -85,12 +85,16 @@ typedef struct lsh_disc {
     int32_t recheck;  /* 0: the sketch is summed exactly in fixed point (each
                          term truncated to a multiple of 2^-k, k chosen per row
                          so no bin can overflow) and discretised in FP32.  Such
-                         a code differs from the FP64 evaluation only when v/w
-                         lies within sqrt(m) * scale * (c_max + 1) * 2^-k / w +
-                         2^-22 * |v/w| of an integer (c_max: the largest bin
-                         population); at |v/w| < 128 and unit-scale rows this
-                         is far below 1e-4 (tiny w or huge values can exceed
-                         it: use recheck).  1: every component whose value lies
+                         a code differs from the FP64 evaluation only when its
+                         value v = (sqrt(m) y + b) / w lies within
+                         sqrt(m) * scale * (c_max + s + 1) * 2^-k / w +
+                         2^-20 * (1 + |v|) of an integer (c_max: the largest bin
+                         population, s: the times a long row's bins were
+                         rescaled); at |v| < 128 and unit-scale rows this is
+                         far below 1e-4, while huge values (|v| near 2^23 and
+                         above) make every code uncertain: use recheck there.
+                         counters[0] counts these components.  1: every
+                         component whose value lies
                          within a rigorous bound of its error from a bin edge
                          (E2LSH) or from zero (SRP) is recomputed in FP64 in
                          ascending coordinate order, so codes equal those of an
@@ -116,7 +120,12 @@ typedef struct lsh_out {
     int32_t *codes;     /* [n][m] E2LSH codes (int32, saturated) or SRP bits (0/1) */
     float *proj;        /* [n][m] projection y before any sqrt(m) scale, row scale applied */
     uint64_t *counters; /* [4], accumulated (not reset) by the call:
-                           [0] components recomputed in FP64 (recheck = 1),
+                           [0] recheck = 1: components recomputed in FP64;
+                               recheck = 0 (CS/HCS): components whose FP32
+                               value lies within the fast path's error
+                               bound of a bin edge (E2LSH) or of zero (SRP),
+                               the only ones whose code may differ from the
+                               FP64 evaluation's,
                            [1] of those, components whose code changed,
                            [2] E2LSH codes that saturated to the int32 range,
                            [3] coordinates whose hash state is out of range

@@ -294,7 +294,37 @@ struct RowFix {
     float af;     // fs * sqrt(m) / w (fast E2LSH path)
     double s2k;   // scale * 2^-k in FP64 (exact)
     double ey;    // bound on |y - y_fp64| before the per-component term (recheck)
+    float efast;  // fast path: bound on |v - v_fp64| in units of w, before the |v| term
+    int32_t eunits; // fast path: bound on |sum - y 2^k / scale| in fixed-point units
 };
+
+// Fast path, counters requested: the components whose FP32 value v =
+// af * sum + b/w lies within its error bound of a bin edge, so that their
+// code may differ from the FP64 evaluation's.  The bound is the fixed-point
+// truncation (rf.efast) plus the FP32 rounding of the sum's conversion, of
+// af and of the FMA (2^-20 |v| covers them; |v| >= 2^23 is always counted).
+__device__ __forceinline__ unsigned fast_near_e2lsh(const HashArgs &a, const WaveLds &w,
+                                                    const float *bl, const RowFix &rf)
+{
+    unsigned c = 0;
+    for (int32_t l = lane_id(); l < a.m; l += kWave) {
+        const int pl = bin_pos(l);
+        const float v = fmaf(rf.af, (float)w.bins[pl], bl[pl]);
+        c += fabsf(v - rintf(v)) <= rf.efast + fabsf(v) * 0x1.0p-20f ? 1u : 0u;
+    }
+    return c;
+}
+
+// SRP fast path: the bit of a component is certain when |sum| exceeds the
+// truncation bound, else it is counted.
+__device__ __forceinline__ unsigned fast_near_srp(const HashArgs &a, const WaveLds &w,
+                                                  const RowFix &rf)
+{
+    unsigned c = 0;
+    for (int32_t l = lane_id(); l < a.m; l += kWave)
+        c += abs(w.bins[bin_pos(l)]) <= rf.eunits ? 1u : 0u;
+    return c;
+}
 
 // Exact FP64 value of component l of row `row`, summed in ascending
 // coordinate order exactly as an FP64 evaluation of the definition would.
@@ -492,6 +522,8 @@ __device__ void epilogue_e2lsh(const HashArgs &a, const uint32_t *tab, const Wav
 {
     const int lane = lane_id();
     if constexpr (!RECHECK) {
+        if (a.counters)
+            nflag += fast_near_e2lsh(a, w, bl, rf);
         if (a.proj) {
             for (int32_t l = lane; l < a.m; l += kWave)
                 a.proj[row * a.m + l] = (float)w.bins[bin_pos(l)] * rf.fs;
@@ -537,6 +569,8 @@ __device__ void epilogue_srp(const HashArgs &a, const uint32_t *tab, const WaveL
 {
     const int lane = lane_id();
     if constexpr (!RECHECK) {
+        if (a.counters)
+            nflag += fast_near_srp(a, w, rf);
         if (!a.codes && !a.proj) {
             if (a.keys) {
                 for (int t = lane; t < a.L; t += kWave) {
@@ -764,6 +798,10 @@ void hash_kernel(HashArgs a)
         } else {
             rf.ey = 0.0;
         }
+        // fast path: the truncation leaves sum within c_max + nres units of
+        // y 2^k / scale (each term truncates by < 1 unit, each shift by < 1)
+        rf.eunits = (int32_t)(cmax + (uint32_t)nres);
+        rf.efast = rf.af * (float)(cmax + (uint32_t)nres + 1u) + 0x1.0p-20f;
         // every code lies in [-128, 127] when sqrt(m) * scale * c_max * max|x| / w
         // < 126: |sum| <= c_max * max|x| * 2^k (terms truncate toward zero)
         // and b/w is in [0, 1); the margin covers the FP32 rounding of the bound

@@ -43,9 +43,10 @@ def test_long_rows_growing_magnitude_recheck_exact(d, family):
     """Long rows whose magnitude grows along the row: every later piece raises
     the exponent, so the bins are shifted several times per row.  The FP64
     recheck must still reproduce the oracle exactly, and without it the
-    projection stays within 1e-5 * ||x||.  (The codes of the fast path are
-    the FP32 evaluation: with |sqrt(m) y| near 1e6 its rounding exceeds the
-    oracle's fixed 1e-4 * w near-edge band, so they are not compared.)"""
+    projection stays within 1e-5 * ||x||.  (The fast path's codes are the
+    FP32 evaluation: with |sqrt(m) y| near 1e6 its error exceeds the oracle's
+    fixed 1e-4 * w near-edge band; the counting test below checks that the
+    fast path counts them.)"""
     dev()
     n, K, L = 400, 16, 32
     g = np.random.default_rng(5)
@@ -61,6 +62,53 @@ def test_long_rows_growing_magnitude_recheck_exact(d, family):
     kw.update(codes=False, keys=False)
     out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), proj=True, **kw)
     compare_hash(out, ref, x64, K, L, what=f"growing d={d}")
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+@pytest.mark.parametrize("growing", [False, True])
+def test_fast_path_counts_its_uncertain_components(family, growing):
+    """Without the recheck, counters[0] counts the components whose FP32 value
+    lies within the fast path's error bound of a bin edge (E2LSH) or of zero
+    (SRP).  Every code that differs from the FP64 oracle's must be one of
+    them, so the mismatches never outnumber the count, and every value beyond
+    2^23 is counted.  Rows whose magnitude grows along the row make the FP32
+    codes wrong in places."""
+    dev()
+    n, K, L = 400, 16, 32
+    m = K * L
+    if growing:
+        d = 4096
+        g = np.random.default_rng(8)
+        x = (g.standard_normal((n, d)) * np.exp2(np.arange(d) // 1024 * 5.0)).astype(np.float32)
+        h, s = synth.cs_state(d, m, 9)
+        b = synth.shifts(m, 4.0, 9)
+    else:
+        d = 784
+        x, h, s, b = _cs_case(n, d, K, L, "sparse", 91)
+    x64 = x.astype(np.float64)
+    ref = oracle.hash_points(x64, family, K, L, kind="cs", w=4.0, b=b, h=h, s=s)
+    cnt = to_dev(np.zeros(4, np.uint64))
+    out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=family, K=K, L=L, w=4.0,
+                          b=to_dev(b), codes=True, counters=cnt)
+    c = to_host(cnt, np.uint64)
+    diff = int((to_host(out["codes"]) != ref["codes"]).sum())
+    assert diff <= int(c[0]), (diff, c)
+    if family == oracle.E2LSH:
+        v = (math.sqrt(m) * ref["y"] + b) / 4.0
+        huge = int((np.abs(v) >= 2.0 ** 23).sum())
+        assert int(c[0]) >= huge
+    if growing and family == oracle.E2LSH:
+        assert diff > 0     # the case does reach codes the FP32 path gets wrong
+    if family == oracle.E2LSH and not growing:
+        assert int(c[0]) < n * m // 100     # ordinary rows: a small fraction is uncertain
+    if family == oracle.SRP:
+        # a component whose coordinates are all zero sums to exactly 0, which
+        # the bound cannot tell from a sum truncated to 0: it is counted
+        assert int(c[0]) >= int((ref["y"] == 0).sum())
+    # the same call without counters gives the same codes
+    again = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=family, K=K, L=L, w=4.0,
+                            b=to_dev(b), codes=True)
+    assert (to_host(again["codes"]) == to_host(out["codes"])).all()
 
 
 @pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
@@ -335,7 +383,7 @@ def test_invalid_hash_state_is_counted():
     h[[3, 77, 200]] = K * L + np.array([0, 5, 1000])
     cnt = to_dev(np.zeros(4, np.uint64))
     lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=1, K=K, L=L, counters=cnt)
-    assert to_host(cnt, np.uint64).tolist() == [0, 0, 0, 3]
+    assert to_host(cnt, np.uint64).tolist()[1:] == [0, 0, 3]
     slot = synth.component_slots(K * L, 407)
     slot[5] = K * L
     h2, _ = synth.cs_state(d, K * L, 408)
