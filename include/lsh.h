@@ -173,7 +173,13 @@ size_t lsh_hash_workspace_bytes(int32_t d, int32_t m, int32_t recheck);
  * cs_consine_lsh): y_l = sum over j with h[j] = l of s[j] * x_j, then the
  * family's discretisation, codes and keys.
  *   h: [d] bins in [0, m); s: [d] signs, each +1 or -1.
- * Requires m <= 16384.  EINVAL on bad shapes, ENOMEM if ws_bytes is short. */
+ * Limits: m <= 16384, and one wave's LDS share must fit a CU's 160 KB: its
+ * bins take 4 (m + m/16 + 64) bytes rounded up to a power of two, the shifts
+ * 4 (m + m/16) bytes, the key seeds 16 L bytes, and the row's hash entries
+ * about 4 d bytes (d rounded up to a multiple of 2048 for rows longer than
+ * 1024 elements): m reaches about 8192 (short rows) and d about 38,000
+ * (small m), one wave per workgroup at the limits.  EINVAL names the bytes
+ * needed.  EINVAL on bad shapes, ENOMEM if ws_bytes is short. */
 lsh_status lsh_hash_cs(const lsh_points *pts, const uint32_t *h, const int8_t *s,
                        const lsh_disc *disc, const lsh_out *out, void *workspace,
                        size_t ws_bytes, void *stream);

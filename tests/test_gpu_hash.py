@@ -416,3 +416,43 @@ def test_dense_bf16_parity(n, d, K, L, family):
                                   b=to_dev(b) if family == 0 else None, codes=True, proj=True)
     compare_hash(out, ref, x64, K, L, weight_max=float(np.abs(R16).max()),
                  what=f"dense bf16 n={n} d={d}")
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+@pytest.mark.parametrize("n,d,K,L", [
+    (37, 32768, 16, 64),   # longest row the recheck takes: 128 KB of row hash entries, one wave
+    (50, 64, 32, 256),     # m = 8192: one wave; too many keys to stage, stored directly
+])
+def test_hash_at_the_lds_limits(n, d, K, L, family):
+    """Shapes at the edge of what one CU's LDS holds run with one wave per
+    workgroup and still match the FP64 oracle exactly (recheck on)."""
+    dev()
+    m = K * L
+    x = synth.gaussian_clusters(n, d, 5, 0.1, 3 + d)
+    h, s = synth.cs_state(d, m, 4 + d)
+    b = synth.shifts(m, 4.0, 4 + d)
+    x64 = x.astype(np.float64)
+    ref = oracle.hash_points(x64, family, K, L, kind="cs", w=4.0, b=b, h=h, s=s)
+    out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=family, K=K, L=L, w=4.0,
+                          b=to_dev(b), codes=True, proj=True, recheck=True)
+    compare_hash(out, ref, x64, K, L, exact=True, what=f"lds limit d={d} m={m}")
+
+
+def test_hash_beyond_the_lds_limits_is_refused():
+    """m = 16384 bins do not fit one wave's LDS share, and the recheck takes
+    at most 32768 coordinates: both are refused with EINVAL before any
+    launch (the counters passed are left untouched)."""
+    import torch
+    device = dev()
+    n = 8
+    for d, K, L, rc, msg in [(64, 64, 256, False, "LDS"), (32769, 16, 4, True, "d <= 32768")]:
+        m = K * L
+        x = torch.ones((n, d), dtype=torch.float32, device=device)
+        h = torch.zeros(d, dtype=torch.int32, device=device)
+        s = torch.ones(d, dtype=torch.int8, device=device)
+        b = torch.zeros(m, dtype=torch.float32, device=device)
+        cnt = torch.full((4,), 7, dtype=torch.int64, device=device)
+        with pytest.raises(lsh.LshError, match=msg):
+            lsh.lsh_hash_cs(x, h, s, family=0, K=K, L=L, w=4.0, b=b, recheck=rc, counters=cnt)
+        torch.cuda.synchronize()
+        assert (cnt == 7).all()
