@@ -9,14 +9,16 @@
 // table's K codes into its 64-bit bucket key (Section 3.1).
 //
 // Work decomposition:
-//   * a workgroup of W waves shares the packed hash table (one 16-bit entry
-//     per coordinate: LDS slot of its bin << 1 | sign), built once per
-//     workgroup from h/s (CS) or from the per-mode tables (HCS), together
-//     with the largest bin population c_max;
-//   * each wave hashes blocks of RB consecutive rows.  A whole row is loaded
-//     into registers with 16-byte loads (chunk c of the row in lane c mod 64)
-//     -- two rows at a time when they are short, so the second row's loads
-//     are in flight while the first is summed;
+//   * a workgroup of W waves shares the hash table (one 32-bit entry per
+//     coordinate: byte offset of its bin's LDS slot, sign in bit 31), built
+//     once per workgroup from h/s (CS) or from the per-mode tables (HCS),
+//     together with the largest bin population c_max; a lane keeps the
+//     entries of its chunks in registers when a row has at most 1024
+//     elements;
+//   * each wave hashes rows of blocks of RB consecutive rows.  A row is
+//     loaded into registers with 16-byte loads (chunk c of the row in lane
+//     c mod 64), the wave's next row in flight while one is summed; long
+//     rows are read in pieces of 1024 elements, the next piece in flight;
 //   * fixed-point sums: LDS float atomics are slow on this GPU, integer ones
 //     run at streaming speed.  Each row gets an exponent k from its largest
 //     magnitude 2^e and c_max (k = 31 - ceil(log2(c_max + 1)) - e), every
@@ -27,13 +29,13 @@
 //     than c * 2^-k for a bin of c terms;
 //   * after a row, the wave discretises its bins (E2LSH: one lane per table,
 //     bins padded one word per 16 so those reads are conflict-free; SRP: one
-//     lane per component plus ballots) and stores the row's L keys; a wave's
-//     consecutive rows fill the same 64-byte key lines in L2 before they are
-//     written back.  LDS per wave is just the bins, so three 8-wave
-//     workgroups fit on a CU.
-// The optional FP64 recheck recomputes, in ascending coordinate order and in
-// FP64, every component whose value lies within the rigorous bound of its
-// error from a bin edge (E2LSH) or from zero (SRP).
+//     lane per component plus ballots) and stages the row's L keys in LDS;
+//     after each block the workgroup writes them as 256-byte runs per table.
+// With the FP64 recheck, a component is evaluated in FP64 from the stored
+// values, in ascending coordinate order, when its FP32 value lies within the
+// rigorous bound of its error from a bin edge (E2LSH) or its fixed-point sum
+// within the truncation bound of zero (SRP); the other codes already equal
+// the FP64 evaluation's.
 
 #include <math.h>
 #include <stdarg.h>
@@ -293,7 +295,6 @@ struct RowFix {
     float fs;     // scale * 2^-k as FP32 (may underflow for tiny rows; fast path only)
     float af;     // fs * sqrt(m) / w (fast E2LSH path)
     double s2k;   // scale * 2^-k in FP64 (exact)
-    double ey;    // bound on |y - y_fp64| before the per-component term (recheck)
     float efast;  // fast path: bound on |v - v_fp64| in units of w, before the |v| term
     int32_t eunits; // fast path: bound on |sum - y 2^k / scale| in fixed-point units
 };
@@ -310,7 +311,7 @@ __device__ __forceinline__ unsigned fast_near_e2lsh(const HashArgs &a, const Wav
     for (int32_t l = lane_id(); l < a.m; l += kWave) {
         const int pl = bin_pos(l);
         const float v = fmaf(rf.af, (float)w.bins[pl], bl[pl]);
-        c += fabsf(v - rintf(v)) <= rf.efast + fabsf(v) * 0x1.0p-20f ? 1u : 0u;
+        c += fabsf(v - rintf(v)) > rf.efast + fabsf(v) * 0x1.0p-20f ? 0u : 1u;
     }
     return c;
 }
@@ -326,68 +327,134 @@ __device__ __forceinline__ unsigned fast_near_srp(const HashArgs &a, const WaveL
     return c;
 }
 
-// Exact FP64 value of component l of row `row`, summed in ascending
-// coordinate order exactly as an FP64 evaluation of the definition would.
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// FP64 value of component l of row `row`, summed in ascending coordinate
+// order exactly as an FP64 evaluation of the definition would, by one lane.
 template <int DT>
-__device__ double exact_component(const HashArgs &a, const uint32_t *tab, int64_t row, double scale,
-                                  int32_t l)
+__device__ double exact_component_lane(const HashArgs &a, const uint32_t *tab, int64_t row,
+                                       double scale, int32_t l)
 {
     double y = 0.0;
-    uint32_t p0 = a.csr_off[l], p1 = a.csr_off[l + 1];
+    const uint32_t p0 = a.csr_off[l], p1 = a.csr_off[l + 1];
     for (uint32_t p = p0; p < p1; ++p) {
-        uint32_t j = a.csr_idx[p];
-        double xv = __dmul_rn(scale, (double)scalar_value<DT>(a.x, row * a.ld + j));
+        const uint32_t j = a.csr_idx[p];
+        const double xv = __dmul_rn(scale, (double)scalar_value<DT>(a.x, row * a.ld + j));
         y = __dadd_rn(y, (tab[j] >> 31) ? -xv : xv);
+    }
+    return y;
+}
+
+// A step of 64 components with more flagged ones than this evaluates them
+// lane by lane, in parallel (each lane's dependent loads then overlap the
+// others'); fewer are evaluated one after another by the whole wave.
+constexpr int kWaveEvalMax = 16;
+
+// FP64 value of component l (the same in every lane) of row `row`, summed
+// in ascending coordinate order exactly as an FP64 evaluation of the
+// definition would, by the whole wave: each lane loads one term of the bin
+// (64 at a time, the coordinates from the bin table), then the terms are
+// added in order through readlane.  Every term scale * x_j is exact in FP64.
+template <int DT>
+__device__ double exact_component_wave(const HashArgs &a, const uint32_t *tab, int64_t row,
+                                       double scale, int32_t l)
+{
+    const int lane = lane_id();
+    const uint32_t p0 = a.csr_off[l], p1 = a.csr_off[l + 1];
+    double y = 0.0;
+    for (uint32_t p = p0; p < p1; p += kWave) {
+        const uint32_t cnt = min(p1 - p, (uint32_t)kWave);
+        double t = 0.0;
+        if ((uint32_t)lane < cnt) {
+            const uint32_t j = a.csr_idx[p + lane];
+            const double xv = __dmul_rn(scale, (double)scalar_value<DT>(a.x, row * a.ld + j));
+            t = (tab[j] >> 31) ? -xv : xv;
+        }
+        for (uint32_t q = 0; q < cnt; ++q)
+            y = __dadd_rn(y, readlane_f64(t, (int)q));
     }
     return y;
 }
 
 // ------------------------------------------------------------- the epilogue
 
-// Code of E2LSH component l (Definition CS_Eucl_LSH): floor((sqrt(m) y + b)/w).
-template <int DT, bool RECHECK>
-__device__ __forceinline__ int32_t e2lsh_code(const HashArgs &a, const uint32_t *tab,
-                                              const WaveLds &w, const float *bl, int64_t row,
-                                              const RowFix &rf, int32_t l, bool count,
-                                              unsigned &nflag, unsigned &nchg, unsigned &nsat)
+// Fast-path code of E2LSH component l (Definition CS_Eucl_LSH):
+// floor((sqrt(m) y + b)/w) in FP32; bl holds b / w and the row factor
+// sqrt(m) * scale * 2^-k / w is folded into rf.af.
+__device__ __forceinline__ int32_t e2lsh_code_fast(const WaveLds &w, const float *bl,
+                                                   const RowFix &rf, int32_t l, bool count,
+                                                   unsigned &nsat)
 {
     const int pl = bin_pos(l);
-    const int32_t isum = w.bins[pl];
-    double cd;
-    if constexpr (!RECHECK) {
-        // bl holds b / w here; the row factor sqrt(m) * scale * 2^-k / w is folded in
-        // (the projection output is written by the caller on this path)
-        float v = fmaf(rf.af, (float)isum, bl[pl]);
-        cd = (double)floorf(v);
-    } else {
-        double y64 = (double)isum * rf.s2k;
-        double t = __dmul_rn(a.alpha64, y64);
-        double b64 = (double)bl[pl];
-        double v = __dadd_rn(t, b64);
-        double q = a.w_pow2 ? v * a.inv_w64 : v / a.w64;
-        cd = floor(q);
-        double Ey = rf.ey + fabs(y64) * 0x1.0p-51;
-        double Ev = a.alpha64 * Ey * (1.0 + 1e-12) + 0x1.0p-50 * (fabs(t) + fabs(v) + fabs(b64));
-        double dist = fabs(v - a.w64 * rint(q));
-        if (dist <= Ev) {
-            double ye = exact_component<DT>(a, tab, row, (double)rf.scale, l);
-            double ve = __dadd_rn(__dmul_rn(a.alpha64, ye), b64);
-            double ce = floor(ve / a.w64);
-            if (count) {
-                ++nflag;
-                nchg += ce != cd;
-            }
-            cd = ce;
-            y64 = ye;
-        }
-        if (a.proj && count)
-            a.proj[row * a.m + l] = (float)y64;
-    }
+    const float v = fmaf(rf.af, (float)w.bins[pl], bl[pl]);
     unsigned sat = 0;
-    int32_t ci = floor_to_i32(cd, sat);
+    const int32_t ci = floor_to_i32((double)floorf(v), sat);
     if (count)
         nsat += sat;
     return ci;
+}
+
+// Recheck: the E2LSH codes of the row, lane per component, 64 components
+// per step, each code written over its bin in LDS.  An FP32 screen takes
+// the fast path's value v = (sqrt(m) y + b) / w and its error bound
+// (rf.efast, one unit wider for the FP64 reference's own rounding; the FP32
+// rounding of b / w lies inside the 2^-20 term).  Outside the bound floor(v)
+// is the FP64 evaluation's code; the components of a step inside it (a NaN,
+// infinite or |v| >= 2^23 value always is) are evaluated one after another
+// by the whole wave in FP64 from the stored values.
+template <int DT>
+__device__ void recheck_e2lsh_codes(const HashArgs &a, const uint32_t *tab, const WaveLds &w,
+                                    const float *bl, int64_t row, const RowFix &rf,
+                                    unsigned &nflag, unsigned &nchg, unsigned &nsat)
+{
+    const int lane = lane_id();
+    for (int32_t l0 = 0; l0 < a.m; l0 += kWave) {
+        const int32_t l = l0 + lane;
+        const bool in = l < a.m;
+        const int pl = bin_pos(in ? l : l0);
+        const int32_t isum = w.bins[pl];
+        const float v32 = fmaf(rf.af, (float)isum, bl[pl] * a.inv_w32);
+        double cd = (double)floorf(v32);
+        double y = (double)isum * rf.s2k;
+        const bool near = in && !(fabsf(v32 - rintf(v32)) >
+                                  rf.efast + rf.af + fabsf(v32) * 0x1.0p-20f);
+        auto take = [&](double ye) {
+            const double ce = floor(__dadd_rn(__dmul_rn(a.alpha64, ye), (double)bl[pl]) / a.w64);
+            ++nflag;
+            nchg += ce != cd;
+            cd = ce;
+            y = ye;
+        };
+        const uint64_t flagged = __ballot(near);
+        if (__popcll(flagged) > kWaveEvalMax) {
+            if (near)
+                take(exact_component_lane<DT>(a, tab, row, (double)rf.scale, l));
+        } else {
+            for (uint64_t fl = flagged; fl; fl &= fl - 1) {
+                const int q = (int)__builtin_ctzll(fl);
+                const double ye =
+                    exact_component_wave<DT>(a, tab, row, (double)rf.scale, l0 + q);
+                if (lane == q)
+                    take(ye);
+            }
+        }
+        if (in) {
+            unsigned sat = 0;
+            const int32_t ci = floor_to_i32(cd, sat);
+            nsat += sat;
+            if (a.codes)
+                a.codes[row * a.m + l] = ci;
+            if (a.proj)
+                a.proj[row * a.m + l] = (float)y;
+            w.bins[pl] = ci; // this step's bins were read above
+        }
+    }
 }
 
 // floor(v) as int32 in one instruction (v_cvt_flr_i32_f32); callers pass
@@ -521,7 +588,18 @@ __device__ void epilogue_e2lsh(const HashArgs &a, const uint32_t *tab, const Wav
                                unsigned &nsat)
 {
     const int lane = lane_id();
-    if constexpr (!RECHECK) {
+    if constexpr (RECHECK) {
+        recheck_e2lsh_codes<DT>(a, tab, w, bl, row, rf, nflag, nchg, nsat);
+        wave_sync();
+        for (int t = lane; t < a.L; t += kWave) {
+            const int32_t l0 = t * a.K;
+            const uint64_t key = e2lsh_key(a.K, hinit[2 * t], hinit[2 * t + 1],
+                                           [&](int r, bool) { return w.bins[bin_pos(l0 + r)]; });
+            if (a.keys)
+                emit_key(a, t, row, slot, key);
+        }
+        return;
+    } else {
         if (a.counters)
             nflag += fast_near_e2lsh(a, w, bl, rf);
         if (a.proj) {
@@ -550,8 +628,7 @@ __device__ void epilogue_e2lsh(const HashArgs &a, const uint32_t *tab, const Wav
     for (int t = lane; t < a.L; t += kWave) {
         const int32_t l0 = t * a.K;
         uint64_t key = e2lsh_key(a.K, hinit[2 * t], hinit[2 * t + 1], [&](int r, bool first) {
-            int32_t c = e2lsh_code<DT, RECHECK>(a, tab, w, bl, row, rf, l0 + r, first, nflag,
-                                                nchg, nsat);
+            const int32_t c = e2lsh_code_fast(w, bl, rf, l0 + r, first, nsat);
             if (first && a.codes)
                 a.codes[row * a.m + l0 + r] = c;
             return c;
@@ -594,26 +671,41 @@ __device__ void epilogue_srp(const HashArgs &a, const uint32_t *tab, const WaveL
     uint64_t mine = 0;
     for (int g = 0; g < ngroups; ++g) {
         int32_t l = g * kWave + lane;
-        bool bit = false;
-        if (l < a.m) {
-            const int32_t isum = w.bins[bin_pos(l)];
-            bit = isum > 0;
-            float yout = 0.0f;
-            if (a.proj)
-                yout = (float)isum * rf.fs;
-            if constexpr (RECHECK) {
-                double y64 = (double)isum * rf.s2k;
-                double Ey = rf.ey + fabs(y64) * 0x1.0p-51;
-                if (fabs(y64) <= Ey) {
-                    double ye = exact_component<DT>(a, tab, row, (double)rf.scale, l);
-                    bool be = ye > 0.0;
-                    ++nflag;
-                    nchg += be != bit;
-                    bit = be;
-                    y64 = ye;
+        const bool in = l < a.m;
+        const int32_t isum = w.bins[bin_pos(in ? l : 0)];
+        bool bit = in && isum > 0;
+        float yout = 0.0f;
+        if (a.proj)
+            yout = (float)isum * rf.fs;
+        if constexpr (RECHECK) {
+            // the sign is certain outside the truncation bound, widened by one
+            // unit for the FP64 reference's own rounding (below one unit while
+            // c_max < 2^20); the others are evaluated by the whole wave
+            double y64 = (double)isum * rf.s2k;
+            const bool near = in && abs(isum) <= rf.eunits + 1;
+            auto take = [&](double ye) {
+                const bool be = ye > 0.0;
+                ++nflag;
+                nchg += be != bit;
+                bit = be;
+                y64 = ye;
+            };
+            const uint64_t flagged = __ballot(near);
+            if (__popcll(flagged) > kWaveEvalMax) {
+                if (near)
+                    take(exact_component_lane<DT>(a, tab, row, (double)rf.scale, l));
+            } else {
+                for (uint64_t fl = flagged; fl; fl &= fl - 1) {
+                    const int q = (int)__builtin_ctzll(fl);
+                    const double ye =
+                        exact_component_wave<DT>(a, tab, row, (double)rf.scale, g * kWave + q);
+                    if (lane == q)
+                        take(ye);
                 }
-                yout = (float)y64;
             }
+            yout = (float)y64;
+        }
+        if (in) {
             if (a.codes)
                 a.codes[row * a.m + l] = bit ? 1 : 0;
             if (a.proj)
@@ -788,18 +880,11 @@ void hash_kernel(HashArgs a)
         rf.s2k = ldexp((double)rf.scale, -k);
         rf.fs = (float)rf.s2k;
         rf.af = rf.fs * a.alpha32 * a.inv_w32;
-        if constexpr (RECHECK) {
-            // truncation: each term off by < 2^-k (times the scale), a bin has
-            // <= c_max terms, plus one unit per shift; plus the FP64
-            // reference's own rounding (c_max^2 * 2^(e-52) bounds
-            // gamma_{c-1} * sum|terms|)
-            rf.ey = (double)rf.scale * ((double)(cmax + nres) * ldexp(1.0, -k) +
-                                        (double)cmax * (double)cmax * ldexp(1.0, e - 51));
-        } else {
-            rf.ey = 0.0;
-        }
-        // fast path: the truncation leaves sum within c_max + nres units of
-        // y 2^k / scale (each term truncates by < 1 unit, each shift by < 1)
+        // the truncation leaves sum within c_max + nres units of y 2^k / scale
+        // (each term truncates by < 1 unit, each shift by < 1).  The FP64
+        // reference's own rounding, gamma_{c-1} * sum|terms| <= c_max^2 *
+        // 2^(e-52), is below one unit: 2^(e+k) = 2^(31-hr) and c_max < 2^hr
+        // with hr <= 16 (c_max <= d <= 32768).
         rf.eunits = (int32_t)(cmax + (uint32_t)nres);
         rf.efast = rf.af * (float)(cmax + (uint32_t)nres + 1u) + 0x1.0p-20f;
         // every code lies in [-128, 127] when sqrt(m) * scale * c_max * max|x| / w
@@ -1016,30 +1101,40 @@ void hash_kernel(HashArgs a)
 namespace lsh {
 
 constexpr int kCsrMaxD = 32768;
+constexpr int kCsrThreads = 1024;
+constexpr int kCsrWaves = kCsrThreads / kWave;
+constexpr int kCsrWaveSort = 256; // largest bin whose coordinates one wave orders by rank
 
-__global__ __launch_bounds__(1024) void csr_kernel(HashArgs a, uint32_t *off, uint32_t *idx,
-                                                   uint32_t *cmax, int p2)
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x)
 {
-    extern __shared__ uint32_t skeys[];
-    __shared__ uint32_t smax;
-    const int tid = threadIdx.x;
-    uint32_t bad = 0; // counted by the hash kernel
-    if (tid == 0)
-        smax = 0;
-    for (int i = tid; i < p2; i += blockDim.x)
-    {
-        uint32_t neg;
-        skeys[i] = i < a.d ? (table_bin(a, i, bad, neg) << 16) | (uint32_t)i : 0xffffffffu;
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
     }
+    return x;
+}
+
+// Fallback for bins of more than kCsrWaveSort coordinates (a degenerate
+// hash state): a bitonic sort of the (bin << 16 | coordinate) words of all
+// coordinates in LDS, then each bin's start by binary search.
+__device__ void csr_bitonic(const HashArgs &a, uint32_t *skeys, uint32_t *off, uint32_t *idx,
+                            int p2)
+{
+    const int tid = threadIdx.x;
+    uint32_t bad = 0, neg;
+    for (int i = tid; i < p2; i += kCsrThreads)
+        skeys[i] = i < a.d ? (table_bin(a, i, bad, neg) << 16) | (uint32_t)i : 0xffffffffu;
     __syncthreads();
-    // bitonic sort of (bin, coordinate) pairs
     for (int k = 2; k <= p2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < p2; i += blockDim.x) {
-                int ixj = i ^ j;
+            for (int i = tid; i < p2; i += kCsrThreads) {
+                const int ixj = i ^ j;
                 if (ixj > i) {
-                    uint32_t x = skeys[i], y = skeys[ixj];
-                    bool up = (i & k) == 0;
+                    const uint32_t x = skeys[i], y = skeys[ixj];
+                    const bool up = (i & k) == 0;
                     if ((x > y) == up) {
                         skeys[i] = y;
                         skeys[ixj] = x;
@@ -1049,30 +1144,169 @@ __global__ __launch_bounds__(1024) void csr_kernel(HashArgs a, uint32_t *off, ui
             __syncthreads();
         }
     }
-    for (int p = tid; p < a.d; p += blockDim.x)
+    for (int p = tid; p < a.d; p += kCsrThreads)
         idx[p] = skeys[p] & 0xffffu;
-    auto lower = [&](uint32_t key) {
+    for (int bin = tid; bin <= a.m; bin += kCsrThreads) {
+        const uint32_t key = (uint32_t)bin << 16;
         int lo = 0, hi = a.d;
         while (lo < hi) {
-            int mid = (lo + hi) >> 1;
+            const int mid = (lo + hi) >> 1;
             if (skeys[mid] < key)
                 lo = mid + 1;
             else
                 hi = mid;
         }
-        return (uint32_t)lo;
-    };
-    for (int bin = tid; bin <= a.m; bin += blockDim.x) {
-        uint32_t o = lower((uint32_t)bin << 16);
-        off[bin] = o;
-        if (bin < a.m) {
-            uint32_t c = lower((uint32_t)(bin + 1) << 16) - o;
-            atomicMax(&smax, c);
-        }
+        off[bin] = (uint32_t)lo;
+    }
+}
+
+// rank[q] += the number of the c list entries below v[q], for the first QN
+// slots; eight LDS reads in flight per step (a lone read waits out the LDS
+// latency), every lane reading the same address (one broadcast)
+template <int QN>
+__device__ __forceinline__ void csr_rank(const uint32_t *list, uint32_t c, const uint32_t *v,
+                                         uint32_t *rank)
+{
+    uint32_t i = 0;
+    for (; i + 8 <= c; i += 8) {
+        uint32_t x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            x[u] = list[i + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < QN; ++q)
+                rank[q] += x[u] < v[q] ? 1u : 0u;
+    }
+    for (; i < c; ++i) {
+        const uint32_t x = list[i];
+#pragma unroll
+        for (int q = 0; q < QN; ++q)
+            rank[q] += x < v[q] ? 1u : 0u;
+    }
+}
+
+// The coordinates of each bin in ascending order (CSR: off[m + 1], idx[d])
+// and the largest bin population, by one workgroup in LDS: a histogram of
+// the bins, its exclusive scan, a placement of every coordinate at its bin's
+// cursor (in any order), then each bin's coordinates put in ascending order
+// by one wave (a coordinate's rank is the number of the bin's coordinates
+// below it), and the list copied out.  A bin of more than kCsrWaveSort
+// coordinates, or a list that does not fit beside the counts (lds_words),
+// sends the table to the bitonic fallback.
+// LDS: lds_words >= max(m + 1 + d, p2) words, or p2 alone.
+__global__ __launch_bounds__(kCsrThreads) void csr_kernel(HashArgs a, uint32_t *off,
+                                                          uint32_t *idx, uint32_t *cmax, int p2,
+                                                          int lds_words)
+{
+    extern __shared__ uint32_t lds_csr[];
+    __shared__ uint32_t wsum[kCsrWaves], wmax[kCsrWaves];
+    uint32_t *cnt = lds_csr; // [m + 1]: counts, then cursors
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    uint32_t bad = 0, neg; // out-of-range entries are counted by the hash kernel
+    for (int b = tid; b <= a.m; b += kCsrThreads)
+        cnt[b] = 0;
+    // the bins of this thread's coordinates j = tid + k * kCsrThreads, all
+    // loads issued together (kept for the placement below)
+    constexpr int kPer = kCsrMaxD / kCsrThreads;
+    uint32_t jb[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * kCsrThreads;
+        jb[k] = j < a.d ? table_bin(a, j, bad, neg) : 0u;
     }
     __syncthreads();
-    if (tid == 0)
-        *cmax = smax;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+        if (tid + k * kCsrThreads < a.d)
+            atomicAdd(&cnt[jb[k]], 1u);
+    __syncthreads();
+
+    // exclusive scan: thread t owns bins [t * per, t * per + per)
+    const int per = (a.m + kCsrThreads - 1) / kCsrThreads;
+    const int b0 = tid * per;
+    uint32_t tot = 0, mx = 0;
+    for (int i = 0; i < per; ++i) {
+        const int b = b0 + i;
+        if (b < a.m) {
+            tot += cnt[b];
+            mx = max(mx, cnt[b]);
+        }
+    }
+    const uint32_t incl = wave_incl_scan_u32(tot);
+    const uint32_t wm = wave_max_u32(mx);
+    if (lane == kWave - 1)
+        wsum[wid] = incl;
+    if (lane == 0)
+        wmax[wid] = wm;
+    __syncthreads();
+    uint32_t run = incl - tot, cm = 0;
+    for (int w = 0; w < kCsrWaves; ++w) {
+        run += w < wid ? wsum[w] : 0u;
+        cm = max(cm, wmax[w]);
+    }
+    for (int i = 0; i < per; ++i) {
+        const int b = b0 + i;
+        if (b < a.m) {
+            const uint32_t c = cnt[b];
+            off[b] = run;
+            cnt[b] = run;
+            run += c;
+        }
+    }
+    if (tid == 0) {
+        off[a.m] = (uint32_t)a.d;
+        *cmax = cm;
+    }
+    __syncthreads();
+    // uniform: every thread read the same wmax
+    if (cm > (uint32_t)kCsrWaveSort || a.m + 1 + a.d > lds_words) {
+        csr_bitonic(a, lds_csr, off, idx, p2);
+        return;
+    }
+
+    // placement at the cursors (order inside a bin still arbitrary)
+    uint32_t *il = lds_csr + a.m + 1;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int j = tid + k * kCsrThreads;
+        if (j < a.d)
+            il[atomicAdd(&cnt[jb[k]], 1u)] = (uint32_t)j;
+    }
+    __syncthreads(); // cnt[b] is now the end of bin b
+
+    // one wave per bin: its coordinates in registers, ranked against the
+    // bin's list (one broadcast LDS read per coordinate), written in order
+    constexpr int Q = kCsrWaveSort / kWave;
+    for (int b = wid; b < a.m; b += kCsrWaves) {
+        const uint32_t o = b ? cnt[b - 1] : 0u, c = cnt[b] - o;
+        if (c < 2)
+            continue;
+        uint32_t v[Q], rank[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t i = (uint32_t)(q * kWave + lane);
+            v[q] = il[o + min(i, c - 1u)];
+            rank[q] = 0;
+        }
+        // compares only for the slots that hold coordinates (c is uniform)
+        switch ((c + kWave - 1) / kWave) {
+        case 1: csr_rank<1>(il + o, c, v, rank); break;
+        case 2: csr_rank<2>(il + o, c, v, rank); break;
+        case 3: csr_rank<3>(il + o, c, v, rank); break;
+        default: csr_rank<4>(il + o, c, v, rank); break;
+        }
+        wave_sync(); // every lane has read the bin before any lane writes it
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if ((uint32_t)(q * kWave + lane) < c)
+                il[o + rank[q]] = v[q];
+        wave_sync();
+    }
+    __syncthreads();
+    for (int p = tid; p < a.d; p += kCsrThreads)
+        idx[p] = il[p];
 }
 
 // ========================================================================
@@ -1374,11 +1608,15 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         int p2 = 1;
         while (p2 < pts->d)
             p2 <<= 1;
-        size_t clds = (size_t)p2 * 4;
+        // the rank-sort path keeps counts and list in LDS when they fit
+        const size_t list_words = (size_t)a.m + 1 + (size_t)pts->d;
+        const size_t lds_words =
+            list_words * 4 <= 160 * 1024 ? std::max((size_t)p2, list_words) : (size_t)p2;
+        const size_t clds = lds_words * 4;
         LSH_HIP(hipFuncSetAttribute((const void *)csr_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)clds));
-        hipLaunchKernelGGL(csr_kernel, dim3(1), dim3(1024), clds, s, a, (uint32_t *)a.csr_off,
-                           (uint32_t *)a.csr_idx, cmax_ws, p2);
+        hipLaunchKernelGGL(csr_kernel, dim3(1), dim3(kCsrThreads), clds, s, a, (uint32_t *)a.csr_off,
+                           (uint32_t *)a.csr_idx, cmax_ws, p2, (int)lds_words);
         LSH_LAUNCHED("csr_kernel");
     }
 

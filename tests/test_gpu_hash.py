@@ -456,3 +456,30 @@ def test_hash_beyond_the_lds_limits_is_refused():
             lsh.lsh_hash_cs(x, h, s, family=0, K=K, L=L, w=4.0, b=b, recheck=rc, counters=cnt)
         torch.cuda.synchronize()
         assert (cnt == 7).all()
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+@pytest.mark.parametrize("heavy", [2, 256, 257])
+def test_recheck_bin_table_every_path(heavy, family):
+    """The recheck recomputes flagged components from a table of each bin's
+    coordinates in ascending order.  A bin of up to 256 coordinates is ordered
+    by one wave, a larger one sends the table to the full sort: both paths
+    (heavy = 256 and 257 coordinates in one bin) give codes equal to the FP64
+    oracle's, on rows with a wide dynamic range so that many components are
+    flagged and recomputed."""
+    dev()
+    n, d, K, L = 300, 600, 8, 8
+    m = K * L
+    g = np.random.default_rng(heavy)
+    h = np.where(np.arange(d) < heavy, 5, g.integers(0, m - 1, d))
+    h = np.where((np.arange(d) >= heavy) & (h >= 5), h + 1, h).astype(np.uint32)  # skip bin 5
+    s = np.where(g.random(d) < 0.5, -1, 1).astype(np.int8)
+    b = synth.shifts(m, 4.0, 12)
+    x = (g.standard_normal((n, d)) * np.exp2(g.integers(-20, 12, (n, d)))).astype(np.float32)
+    x64 = x.astype(np.float64)
+    ref = oracle.hash_points(x64, family, K, L, kind="cs", w=4.0, b=b, h=h, s=s)
+    cnt = to_dev(np.zeros(4, np.uint64))
+    out = lsh.lsh_hash_cs(to_dev(x), to_dev(h), to_dev(s), family=family, K=K, L=L, w=4.0,
+                          b=to_dev(b), codes=True, recheck=True, counters=cnt)
+    compare_hash(out, ref, x64, K, L, exact=True, what=f"bin table heavy={heavy}")
+    assert int(to_host(cnt, np.uint64)[0]) > 0
