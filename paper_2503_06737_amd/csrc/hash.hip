@@ -745,7 +745,7 @@ template <int DT, bool ALIGNED> constexpr int ALIGNED_VEC() { return ALIGNED ? E
 //   [SRP masks: waves x ceil(m/64) u64]
 template <int FAM, int DT, bool ALIGNED, bool RECHECK, int CH, bool LONG>
 // registers capped so that two workgroups fit per CU (the LDS limit)
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CH * ALIGNED_VEC<DT, ALIGNED>() <= 16 ? 4 : 1)))
+__global__ __launch_bounds__(LONG ? 1024 : 512) __attribute__((amdgpu_waves_per_eu(CH * ALIGNED_VEC<DT, ALIGNED>() <= 16 ? 4 : 1)))
 void hash_kernel(HashArgs a)
 {
     // (the kernel has no static LDS, so this array starts at LDS address 0
@@ -1576,6 +1576,12 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
     int waves = 8;
     while (waves > 1 && lds_for(waves) > lds_max)
         waves >>= 1;
+    // long rows: their hash table (4 bytes per coordinate) is shared by the
+    // workgroup, so sixteen waves may keep more waves resident per CU than
+    // workgroups of eight that each hold a copy
+    if (a.pieces > 1 && waves == 8 && lds_for(16) <= lds_max &&
+        16 * (lds_max / lds_for(16)) > 8 * (lds_max / lds_for(8)))
+        waves = 16;
     if (lds_for(waves) > lds_max && stage_on) {
         stage_on = false; // keys too many to stage: store them directly
         waves = 8;
