@@ -1878,17 +1878,30 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
                        dim3(kSegThreadsS), segs_lds, s, ba);
     hipLaunchKernelGGL((seg_sort_kernel<kSegThreads, kSegTiny>), dim3(1 << wl.bits, L),
                        dim3(kSegThreads), seg_lds, s, ba);
-    hipLaunchKernelGGL(big_pivot_kernel, dim3(wl.big_grid), dim3(kWave), 0, s, ba);
-    hipLaunchKernelGGL(big_count_kernel, dim3(4 * wl.big_grid), dim3(256), 0, s, ba);
-    hipLaunchKernelGGL(big_cscan_kernel, dim3(wl.big_grid), dim3(kWave), 0, s, ba);
-    hipLaunchKernelGGL(big_part_kernel, dim3(2 * wl.big_grid), dim3(kThreads), 0, s, ba);
+    // The big-segment kernels walk lists built on the device, in grid-stride
+    // loops.  Their grids are capped by the most work n keys per table can
+    // give (segments above kSegSmall keys, their kTile tiles, two parts
+    // each), so a small build (a serving insert) does not queue hundreds of
+    // idle whole-CU workgroups behind other streams' work.
+    const int64_t max_big = std::max<int64_t>(1, (int64_t)L * (n / (kSegSmall + 1)));
+    const int64_t max_bt = std::max<int64_t>(1, (int64_t)L * (3 * n / kTile + 1));
+    const int bg = (int)std::min<int64_t>(wl.big_grid, max_big);
+    const int bt4 = (int)std::min<int64_t>(4 * wl.big_grid, max_bt);
+    const int bt2 = (int)std::min<int64_t>(2 * wl.big_grid, max_bt);
+    hipLaunchKernelGGL(big_pivot_kernel, dim3(bg), dim3(kWave), 0, s, ba);
+    hipLaunchKernelGGL(big_count_kernel, dim3(bt4), dim3(256), 0, s, ba);
+    hipLaunchKernelGGL(big_cscan_kernel, dim3(bg), dim3(kWave), 0, s, ba);
+    hipLaunchKernelGGL(big_part_kernel, dim3(bt2), dim3(kThreads), 0, s, ba);
     // the small parts of the split segments: as many workgroups as fit on
     // the 256 CUs at once (four and two per CU), at most two per big segment
-    hipLaunchKernelGGL((part_sort_kernel<kSegThreadsS, 0>), dim3(min(2 * nseg, 4 * 256)),
-                       dim3(kSegThreadsS), segs_lds, s, ba);
-    hipLaunchKernelGGL((part_sort_kernel<kSegThreads, 1>), dim3(min(2 * nseg, 2 * 256)),
-                       dim3(kSegThreads), seg_lds, s, ba);
-    hipLaunchKernelGGL(big_sort_kernel, dim3(wl.big_grid), dim3(kThreads), big_lds, s, ba);
+    const int64_t parts = std::min<int64_t>(2 * nseg, 2 * max_big);
+    hipLaunchKernelGGL((part_sort_kernel<kSegThreadsS, 0>),
+                       dim3((int)std::min<int64_t>(parts, 4 * 256)), dim3(kSegThreadsS),
+                       segs_lds, s, ba);
+    hipLaunchKernelGGL((part_sort_kernel<kSegThreads, 1>),
+                       dim3((int)std::min<int64_t>(parts, 2 * 256)), dim3(kSegThreads), seg_lds,
+                       s, ba);
+    hipLaunchKernelGGL(big_sort_kernel, dim3(bg), dim3(kThreads), big_lds, s, ba);
 
     HeadArgs ha;
     ha.sk = ba.kb;
