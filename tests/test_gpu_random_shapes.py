@@ -1,0 +1,118 @@
+"""A seeded sweep of random shapes through the whole path, each stage against
+the FP64 oracle: the hash (count sketch or higher-order count sketch, E2LSH or
+SRP, FP32 / BF16 / FP8-E4M3FN storage, with and without the FP64 recheck),
+the index built from the GPU keys (bit-exact), and a top-10 query over it.
+The draws reach the kernels' edges: d not a multiple of the 16-byte chunk,
+rows longer than one register load (read in pieces), a single point, K other
+than 8 and 16, m not a multiple of 64."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_06737_amd import lsh, recall, synth
+from gpu_util import compare_hash, dev, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+N_CASES = 64
+
+
+def _draw(i):
+    g = np.random.default_rng([0x5EED, i])
+    c = dict(
+        n=int(g.choice([1, 2, 31, 33, 257, 1000, 2049, 3001])),
+        d=int(g.choice([1, 3, 8, 17, 64, 100, 333, 784, 1024, 1025, 2500, 4096, 5000])),
+        family=int(g.integers(0, 2)),
+        K=int(g.choice([1, 3, 7, 8, 12, 16, 24, 32])),
+        L=int(g.integers(1, 41)),
+        storage=str(g.choice(["f32", "bf16", "fp8"])),
+        recheck=bool(g.integers(0, 2)),
+        hcs=int(g.choice([0, 0, 2, 3])),
+        seed=1000 + i,
+    )
+    c["L"] = max(1, min(c["L"], 2048 // c["K"]))
+    return c
+
+
+def _points(c):
+    x = synth.gaussian_clusters(c["n"], c["d"], 5, 0.1, c["seed"])
+    if c["storage"] == "f32":
+        return x, None, x.astype(np.float64)
+    q, sc = synth.quantise_rows(x, c["storage"])
+    return q, sc, oracle.decode(q, sc)
+
+
+def _hash(c, xs, sc, st, x64, recheck):
+    """GPU hash of stored rows xs (scale sc) and the oracle's of x64."""
+    K, L, fam = c["K"], c["L"], c["family"]
+    okw = dict(w=4.0, b=st["b"])
+    gkw = dict(family=fam, K=K, L=L, w=4.0, b=to_dev(st["b"]), recheck=recheck, codes=True,
+               scale=None if sc is None else to_dev(sc))
+    if c["hcs"]:
+        ref = oracle.hash_points(x64, fam, K, L, kind="hcs", dk=st["dk"], mk=st["mk"],
+                                 hk=st["hk"], sk=st["sk"], **okw)
+        out = lsh.lsh_hash_hcs(to_dev(xs), st["dk"], st["mk"], to_dev(np.concatenate(st["hk"])),
+                               to_dev(np.concatenate(st["sk"])), proj=not recheck, **gkw)
+    else:
+        ref = oracle.hash_points(x64, fam, K, L, kind="cs", h=st["h"], s=st["s"], **okw)
+        out = lsh.lsh_hash_cs(to_dev(xs), to_dev(st["h"]), to_dev(st["s"]), proj=not recheck,
+                              **gkw)
+    return out, ref
+
+
+@pytest.mark.parametrize("i", range(N_CASES))
+def test_random_shape_hash_index_query(i):
+    dev()
+    c = _draw(i)
+    n, d, K, L, fam = c["n"], c["d"], c["K"], c["L"], c["family"]
+    m = K * L
+    print(f"random shape {i}: {c}", flush=True)
+    st = {"b": synth.shifts(m, 4.0, c["seed"] + 1)}
+    if c["hcs"]:
+        st["dk"], st["mk"] = recall.hcs_modes(d, m, c["hcs"])
+        st["hk"], st["sk"] = synth.hcs_state(st["dk"], st["mk"], c["seed"] + 2)
+        assert math.prod(st["dk"]) >= d and math.prod(st["mk"]) == m
+    else:
+        st["h"], st["s"] = synth.cs_state(d, m, c["seed"] + 2)
+    xs, sc, x64 = _points(c)
+
+    # 1. hash: exact with the recheck, else codes equal outside the near-edge band
+    out, ref = _hash(c, xs, sc, st, x64, c["recheck"])
+    compare_hash(out, ref, x64, K, L, exact=c["recheck"], what=f"case {i}")
+
+    # 2. index of the GPU keys: bit-exact against the oracle's grouping of the same keys
+    keys = to_host(out["keys"], np.uint64)
+    ri = oracle.build_index(keys)
+    idx = lsh.lsh_build_index(out["keys"])
+    assert idx.check() == (0, 0)
+    sid, uk, of, nu = idx.arrays()
+    assert to_host(nu).tolist() == ri["nuniq"].tolist()
+    assert (to_host(sid, np.uint32) == ri["sorted_ids"]).all()
+    uk, of = to_host(uk, np.uint64), to_host(of, np.uint32)
+    for t in range(L):
+        u = int(ri["nuniq"][t])
+        assert (uk[t, :u] == ri["ukeys"][t, :u]).all()
+        assert (of[t, :u + 1] == ri["offs"][t, :u + 1]).all()
+
+    # 3. query: the first rows as queries (FP32), hashed with the recheck so
+    # that their keys are the oracle's; candidates and top-10 over the index
+    nq = min(n, 20)
+    Q = x64[:nq].astype(np.float32)
+    qo, qref = _hash(c, Q, None, st, Q.astype(np.float64), True)
+    qk = to_host(qo["keys"], np.uint64)
+    assert (qk == qref["keys"]).all()
+    base = to_dev(xs)
+    ids, sc_g, nc = lsh.lsh_query([idx], base, to_dev(Q), qo["keys"], k=10, metric=fam,
+                                  base_scale=None if sc is None else to_dev(sc))
+    rids, rsc, rnc = oracle.query([ri], x64, Q.astype(np.float64), qk, 10, n, fam)
+    assert (to_host(nc) == rnc).all(), f"case {i}: candidate counts"
+    np.testing.assert_allclose(to_host(sc_g), rsc, rtol=1e-5, atol=1e-5)
+    gids = to_host(ids)
+    for r in range(nq):
+        fin = np.isfinite(rsc[r])
+        kth = rsc[r][fin][-1] if fin.any() else np.inf
+        strict = rsc[r] < kth * (1 - 1e-5) - 1e-5
+        assert set(gids[r][strict]) == set(rids[r][strict]), f"case {i}: query {r}"
+        assert (gids[r][~fin] == -1).all()
