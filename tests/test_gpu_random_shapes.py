@@ -116,3 +116,52 @@ def test_random_shape_hash_index_query(i):
         strict = rsc[r] < kth * (1 - 1e-5) - 1e-5
         assert set(gids[r][strict]) == set(rids[r][strict]), f"case {i}: query {r}"
         assert (gids[r][~fin] == -1).all()
+
+
+def _draw_tables(i):
+    g = np.random.default_rng([0x7AB1E5, i])
+    c = dict(
+        n=int(g.choice([1, 2, 33, 1000, 3001])),
+        d=int(g.choice([1, 5, 17, 64, 300, 784, 1025, 1500])),
+        family=int(g.integers(0, 2)),
+        K=int(g.choice([1, 2, 3, 4, 7, 8, 12, 16])),
+        L=int(g.integers(1, 65)),
+        storage=str(g.choice(["f32", "bf16", "fp8"])),
+        hcs=int(g.choice([0, 0, 2, 3])),
+        seed=5000 + i,
+    )
+    c["L"] = max(1, min(c["L"], 100_000 // c["d"]))   # the per-table state stays small in LDS
+    return c
+
+
+@pytest.mark.parametrize("i", range(32))
+def test_random_shape_per_table_sketches(i):
+    """Per-table sketches (L independent sketches of K) at random shapes:
+    codes and keys against the oracle's L separate sketches, and the index
+    of the GPU keys bit-exact."""
+    dev()
+    c = _draw_tables(i)
+    n, d, K, L, fam = c["n"], c["d"], c["K"], c["L"], c["family"]
+    print(f"random per-table shape {i}: {c}", flush=True)
+    b = synth.shifts(K * L, 4.0, c["seed"] + 1)
+    xs, sc, x64 = _points(c)
+    gkw = dict(family=fam, K=K, L=L, w=4.0, b=to_dev(b) if fam == 0 else None, codes=True,
+               proj=True, scale=None if sc is None else to_dev(sc))
+    if c["hcs"]:
+        dk, mk = recall.hcs_modes(d, K, c["hcs"])
+        hk, sk = synth.hcs_tables_state(dk, mk, L, c["seed"] + 2)
+        splits = np.cumsum(dk)[:-1]
+        ref = oracle.hash_points_tables(x64, fam, K, L, kind="hcs", w=4.0, b=b, dk=dk, mk=mk,
+                                        hk=[np.split(hk[t], splits) for t in range(L)],
+                                        sk=[np.split(sk[t], splits) for t in range(L)])
+        out = lsh.lsh_hash_hcs_tables(to_dev(xs), dk, mk, to_dev(hk), to_dev(sk), **gkw)
+    else:
+        h, s = synth.cs_tables_state(d, K, L, c["seed"] + 2)
+        ref = oracle.hash_points_tables(x64, fam, K, L, kind="cs", w=4.0, b=b, h=h, s=s)
+        out = lsh.lsh_hash_cs_tables(to_dev(xs), to_dev(h), to_dev(s), **gkw)
+    compare_hash(out, ref, x64, K, L, what=f"per-table case {i}")
+    keys = to_host(out["keys"], np.uint64)
+    ri = oracle.build_index(keys)
+    idx = lsh.lsh_build_index(out["keys"])
+    assert idx.check() == (0, 0)
+    assert (to_host(idx.arrays()[0], np.uint32) == ri["sorted_ids"]).all()
