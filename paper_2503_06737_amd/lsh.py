@@ -114,7 +114,8 @@ def _ptr(t):
 
 def points(x: torch.Tensor, scale: torch.Tensor | None = None) -> Points:
     """Describe a 2-D device tensor of points (rows contiguous)."""
-    assert x.dim() == 2 and x.stride(1) == 1, "points must be a row-major 2-D tensor"
+    assert x.dim() == 2 and (x.stride(1) == 1 or x.shape[1] == 1), \
+        "points must be a row-major 2-D tensor"
     if x.dtype == torch.float32:
         dt = F32
     elif x.dtype in (torch.bfloat16, torch.int16, torch.uint16):
@@ -257,7 +258,8 @@ def lsh_hash_dense_bf16(x, scale, Rt, *, family, K, L, w=1.0, b=None, keys=True,
     """Dense E2LSH / SRP with BF16 operands: x [n][d] BF16 bits (int16) with
     float32 row scales, Rt [m][d] BF16 bits (row l = projection vector r_l)."""
     pts = points(x, scale)
-    assert Rt.dim() == 2 and Rt.stride(1) == 1 and Rt.shape[0] == K * L
+    # (a size-1 dimension's stride is arbitrary: torch keeps the transposed one)
+    assert Rt.dim() == 2 and (Rt.stride(1) == 1 or Rt.shape[1] == 1) and Rt.shape[0] == K * L
     o, out = _outputs(x.shape[0], K * L, L, x.device, keys, codes, proj, None)
     disc = _disc(family, K, L, w, b, 0)
     _check(lib().lsh_hash_dense_bf16(C.byref(pts), _ptr(Rt), Rt.stride(0), C.byref(disc),

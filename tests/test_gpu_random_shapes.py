@@ -165,3 +165,50 @@ def test_random_shape_per_table_sketches(i):
     idx = lsh.lsh_build_index(out["keys"])
     assert idx.check() == (0, 0)
     assert (to_host(idx.arrays()[0], np.uint32) == ri["sorted_ids"]).all()
+
+
+def _draw_dense(i):
+    g = np.random.default_rng([0xDE15E, i])
+    c = dict(
+        n=int(g.choice([1, 2, 127, 129, 1000, 3001])),
+        d=int(g.choice([1, 3, 7, 8, 9, 16, 100, 129, 784, 1025])),
+        family=int(g.integers(0, 2)),
+        K=int(g.choice([1, 3, 7, 8, 12, 16, 24, 32])),
+        L=int(g.integers(1, 41)),
+        bf16=bool(g.integers(0, 2)),
+        seed=9000 + i,
+    )
+    c["L"] = max(1, min(c["L"], 2048 // c["K"]))
+    return c
+
+
+@pytest.mark.parametrize("i", range(32))
+def test_random_shape_dense(i):
+    """The dense baselines (FP32 and BF16-operand matrix cores) at random
+    shapes, rows and columns off the 128 x 128 tile and d off the 16-value
+    step: projections within the dense band, codes equal outside the
+    near-edge band, keys equal wherever a table has no near-edge code."""
+    dev()
+    c = _draw_dense(i)
+    n, d, K, L, fam = c["n"], c["d"], c["K"], c["L"], c["family"]
+    m = K * L
+    print(f"random dense shape {i}: {c}", flush=True)
+    x = synth.gaussian_clusters(n, d, 5, 0.1, c["seed"])
+    R = synth.gaussian_matrix(d, m, c["seed"] + 1)
+    b = synth.shifts(m, 4.0, c["seed"] + 2)
+    kw = dict(family=fam, K=K, L=L, w=4.0, b=to_dev(b) if fam == 0 else None, codes=True,
+              proj=True)
+    if c["bf16"]:
+        import torch
+        q, sc = synth.quantise_rows(x, "bf16")
+        x64 = oracle.decode(q, sc)
+        Rb = torch.from_numpy(R).to(torch.bfloat16)
+        R = Rb.to(torch.float32).numpy()                    # the BF16 values, exactly
+        Rt = Rb.T.contiguous().view(torch.int16).to(dev())  # [m][d] bits
+        out = lsh.lsh_hash_dense_bf16(to_dev(q), to_dev(sc), Rt, **kw)
+    else:
+        x64 = x.astype(np.float64)
+        out = lsh.lsh_hash_dense(to_dev(x), to_dev(R), **kw)
+    ref = oracle.hash_points(x64, fam, K, L, kind="dense", w=4.0, b=b, R=R)
+    compare_hash(out, ref, x64, K, L, weight_max=float(np.abs(R).max()),
+                 what=f"dense case {i}")
