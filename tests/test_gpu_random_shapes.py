@@ -212,3 +212,75 @@ def test_random_shape_dense(i):
     ref = oracle.hash_points(x64, fam, K, L, kind="dense", w=4.0, b=b, R=R)
     compare_hash(out, ref, x64, K, L, weight_max=float(np.abs(R).max()),
                  what=f"dense case {i}")
+
+
+def _draw_query(i):
+    g = np.random.default_rng([0x9E41, i])
+    c = dict(
+        n=int(g.choice([1, 40, 3000, 9000])),
+        d=int(g.choice([1, 3, 17, 64, 200, 960])),
+        family=int(g.integers(0, 2)),
+        K=int(g.choice([2, 4, 8])),
+        L=int(g.choice([1, 3, 8, 16])),
+        w=float(g.choice([0.5, 4.0, 64.0])),
+        nseg=int(g.integers(1, 5)),
+        nq=int(g.choice([1, 7, 300, 1100])),
+        k=int(g.choice([1, 3, 10, 33, 64])),
+        storage=str(g.choice(["f32", "bf16", "fp8"])),
+        seed=12000 + i,
+    )
+    c["cuts"] = sorted(int(v) for v in g.integers(0, c["n"] + 1, c["nseg"] - 1))
+    c["watermark"] = int(g.integers(0, c["n"] + 1))
+    if c["w"] >= 64.0 and c["nq"] * c["n"] * c["d"] > 3e8:   # huge buckets: keep the oracle quick
+        c["nq"] = 7
+    return c
+
+
+@pytest.mark.parametrize("i", range(32))
+def test_random_shape_query(i):
+    """Queries at random shapes: 1-4 index segments of contiguous ids (some
+    may be empty), a random watermark, batches of 1 to 1100 queries (both
+    workgroup shapes), k up to 64, buckets wide enough to need several
+    candidate windows, FP32 / BF16 / FP8 bases; candidate counts exact,
+    scores and top-k against the FP64 oracle."""
+    dev()
+    c = _draw_query(i)
+    n, d, K, L, fam, w = c["n"], c["d"], c["K"], c["L"], c["family"], c["w"]
+    m = K * L
+    print(f"random query shape {i}: {c}", flush=True)
+    h, s = synth.cs_state(d, m, c["seed"] + 1)
+    b = synth.shifts(m, w, c["seed"] + 2)
+    hd, sd, bd = to_dev(h), to_dev(s), to_dev(b)
+    xs, sc, x64 = _points(c)
+    kw = dict(family=fam, K=K, L=L, w=w, b=bd if fam == 0 else None, recheck=True)
+    keys = lsh.lsh_hash_cs(to_dev(xs), hd, sd, scale=None if sc is None else to_dev(sc),
+                           **kw)["keys"]
+    okw = dict(kind="cs", w=w, b=b, h=h, s=s)
+    rk = oracle.hash_points(x64, fam, K, L, **okw)["keys"]
+    assert (to_host(keys, np.uint64) == rk).all()
+    bounds = [0] + c["cuts"] + [n]
+    segs, rsegs = [], []
+    for lo, hi in zip(bounds[:-1], bounds[1:]):
+        segs.append(lsh.lsh_build_index(keys[:, lo:hi].contiguous(), id_base=lo))
+        rsegs.append(oracle.build_index(np.ascontiguousarray(rk[:, lo:hi]), lo))
+    g = np.random.default_rng([c["seed"], 1])
+    own = x64[g.integers(0, n, (c["nq"] + 1) // 2)]
+    fresh = synth.gaussian_clusters(c["nq"] // 2, d, 5, 0.1, c["seed"], stream=1)
+    Q = np.concatenate([own, fresh.astype(np.float64)]).astype(np.float32)
+    qk = lsh.lsh_hash_cs(to_dev(Q), hd, sd, **kw)["keys"]
+    rqk = oracle.hash_points(Q.astype(np.float64), fam, K, L, **okw)["keys"]
+    assert (to_host(qk, np.uint64) == rqk).all()
+    ids, scg, nc = lsh.lsh_query(segs, to_dev(xs), to_dev(Q), qk, k=c["k"],
+                                 watermark=c["watermark"], metric=fam,
+                                 base_scale=None if sc is None else to_dev(sc))
+    rids, rsc, rnc = oracle.query(rsegs, x64, Q.astype(np.float64), rqk, c["k"], c["watermark"],
+                                  fam)
+    assert (to_host(nc) == rnc).all(), f"case {i}: candidate counts"
+    np.testing.assert_allclose(to_host(scg), rsc, rtol=1e-5, atol=1e-5)
+    gids = to_host(ids)
+    for r in range(Q.shape[0]):
+        fin = np.isfinite(rsc[r])
+        kth = rsc[r][fin][-1] if fin.any() else np.inf
+        strict = rsc[r] < kth * (1 - 1e-5) - 1e-5
+        assert set(gids[r][strict]) == set(rids[r][strict]), f"case {i}: query {r}"
+        assert (gids[r][~fin] == -1).all()
