@@ -23,13 +23,15 @@ def _setup(n0, d, K, L, w, family, seed):
 
 
 def _serve(n0=3000, d=64, K=8, L=8, w=8.0, family=lsh.E2LSH, n_req=60, max_points=40,
-           budget=60_000, seed=71, inflight=2, realtime=False, storage="f32"):
+           budget=60_000, seed=71, inflight=2, realtime=False, storage="f32", query_streams=2,
+           query_frac=0.7):
     dev()
     x0, h, s, b, qsrc, isrc = _setup(n0, d, K, L, w, family, seed)
-    reqs = serve.poisson_stream(n_req, 1e4, 0.7, max_points, d, qsrc, isrc, seed)
+    reqs = serve.poisson_stream(n_req, 1e4, query_frac, max_points, d, qsrc, isrc, seed)
     srv = serve.Server(to_dev(x0), to_dev(h), to_dev(s), to_dev(b), K=K, L=L, w=w,
                        capacity=n0 + sum(r.points.shape[0] for r in reqs), budget_bytes=budget,
-                       k=10, metric=family, max_inflight=inflight, recheck=True, storage=storage)
+                       k=10, metric=family, max_inflight=inflight, recheck=True, storage=storage,
+                       query_streams=query_streams)
     stats = srv.serve(reqs, realtime=realtime)
     return srv, reqs, stats, (x0, h, s, b, K, L, w, family, storage)
 
@@ -129,3 +131,31 @@ def test_serve_realtime_latency_fields():
     summary = serve.summarize(reqs, stats, max(r.done for r in reqs))
     assert summary["queries"] + summary["inserts"] == 40
     assert all(np.isfinite(r.done) and r.done >= 0 for r in reqs)
+
+
+def _draw_serve(i):
+    g = np.random.default_rng([0x5E7E, i])
+    return dict(n_req=int(g.integers(20, 121)), max_points=int(g.choice([1, 16, 64, 300])),
+                budget=int(g.choice([1, 30_000, 200_000, 10**9])), inflight=int(g.integers(1, 6)),
+                storage=str(g.choice(["f32", "bf16", "fp8"])), family=int(g.integers(0, 2)),
+                query_streams=int(g.integers(1, 4)), query_frac=float(g.choice([0.3, 0.7, 0.95])),
+                seed=200 + i)
+
+
+@pytest.mark.parametrize("i", range(8))
+def test_serve_random_configurations(i):
+    """Random server configurations (budget from one byte to unlimited, 1-5
+    batches in flight, 1-3 query streams, request sizes up to 300 points, any
+    storage and family): every query answer equals the oracle's over exactly
+    the points inserted before it arrived, and the bytes in flight stay within
+    the budget whenever no single request exceeds it."""
+    c = _draw_serve(i)
+    print(f"random serving configuration {i}: {c}", flush=True)
+    fam = c.pop("family")
+    srv, reqs, stats, params = _serve(family=fam, w=8.0 if fam == lsh.E2LSH else 1.0, **c)
+    assert stats.batches >= 1 and stats.max_inflight_seen <= c["inflight"]
+    largest = max(srv._request_bytes(r) for r in reqs)
+    if largest <= c["budget"]:
+        assert stats.peak_bytes <= c["budget"]
+    assert len(srv.segments) <= serve.MAX_SEGMENTS
+    _check_oracle(srv, reqs, params)
