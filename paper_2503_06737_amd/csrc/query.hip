@@ -7,12 +7,12 @@
 // (Section 6 retrieves the top-k this way).
 //
 // One workgroup per query.  Every bucket is an ascending id list, so the
-// union is processed in windows of the id space that hold at most kCap
-// (bucket, id) entries: each window is gathered into LDS, sorted and
-// deduplicated, its distinct ids are scored (one wave per candidate row,
-// coalesced loads), and the window's (score, id) pairs are merged with the
-// running top-k by a bitonic sort of 64-bit (score bits, id) keys.  Memory
-// is bounded whatever the bucket sizes.
+// union is processed in windows of the id space that hold at most 2048 (a
+// query alone) or 1024 (in a batch) (bucket, id) entries: each window is
+// gathered into LDS, sorted and deduplicated, its distinct ids are scored
+// (one wave per candidate row, coalesced loads), and the window's (score,
+// id) pairs are merged with the running top-k by a bitonic sort of 64-bit
+// (score bits, id) keys.  Memory is bounded whatever the bucket sizes.
 
 #include <math.h>
 
@@ -23,15 +23,39 @@
 namespace lsh {
 
 // Threads per query: 512 when the batch has at most one query per CU (a
-// query then has a CU to itself), else 256 (two queries per CU: the LDS
-// limit).
+// query then has a CU to itself), else 256.
 constexpr int kQThreads = 256;
 constexpr int kQThreadsSolo = 512;
-constexpr int kCap = 2048;        // (bucket, id) entries per window
 constexpr int kMaxK = 64;
-constexpr int kSortCap = 4096;    // >= next pow2 of kCap + kMaxK
 constexpr int kMaxSeg = 16;
 constexpr int kMaxLists = 1024;   // nseg * L
+
+constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
+
+// Per workgroup shape: cap, the (bucket, id) entries of a window; nr, the
+// FP32 candidate rows a wave scores together (their loads in flight at
+// once); wpe, the waves per SIMD the registers are sized for.  A solo query
+// takes windows of 2048 entries and six rows per wave.  In a batch, windows
+// of 1024 entries, three rows per wave and at most 128 VGPRs leave the LDS
+// and registers for four queries per CU (two with the solo sizes), so more
+// queries overlap their latency-bound phases.
+template <int QT> struct QShape;
+template <> struct QShape<kQThreadsSolo> {
+    static constexpr int cap = 2048, nr = 6, wpe = 2;
+};
+template <> struct QShape<kQThreads> {
+    static constexpr int cap = 1024, nr = 3, wpe = 4;
+};
+template <int QT> constexpr int sort_cap() { return pow2_at_least(QShape<QT>::cap + kMaxK); }
+
+// LDS of a query workgroup: the query row, five arrays over the nl lists
+// (one with nl + 1 entries), the sort buffer, the top-k and the window's ids.
+template <int QT> size_t query_lds_bytes(int d, int nl)
+{
+    const size_t nlp = (size_t)((nl + 4) & ~3);
+    return (size_t)((d * 4 + 15) & ~15) + 5 * nlp * 4 + 16 +
+           (size_t)(sort_cap<QT>() + kMaxK) * 8 + (size_t)QShape<QT>::cap * 4;
+}
 
 struct QSeg {
     const uint32_t *ids;
@@ -149,11 +173,10 @@ __device__ __forceinline__ void score_rows(const QueryArgs &a, const float *qv,
 
 // The same sums for FP32 rows read as 16-byte chunks (the base pointer
 // 16-byte aligned, ld and d multiples of 4): 4 chunk loads per lane and row
-// cover 1024 elements, so a wave keeps NR = 8 rows in flight within the
-// 63 loads a wave can have outstanding.  Chunk indexes are clamped into the
+// cover 1024 elements, so a wave keeps its NR rows in flight within the 63
+// loads a wave can have outstanding.  Chunk indexes are clamped into the
 // row; the lanes past its end add 0.
 constexpr int kScoreChunks = 4;
-constexpr int kScoreRowsV4 = 6;
 
 template <int NR>
 __device__ __forceinline__ void score_rows_v4(const QueryArgs &a, const float *qv,
@@ -383,17 +406,21 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, u
 }
 
 template <int QT>
-__global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(2))) void query_kernel(QueryArgs a)
+__global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(QShape<QT>::wpe))) void
+query_kernel(QueryArgs a)
 {
     constexpr int QW = QT / kWave;
+    constexpr int kCap = QShape<QT>::cap;
+    constexpr int kSortCap = sort_cap<QT>();
     extern __shared__ __align__(16) unsigned char lds[];
+    const int nlp = (a.nseg * a.L + 4) & ~3; // list arrays, lst_pre's extra entry included
     float *qv = (float *)lds;                                          // [d]
-    uint32_t *lst_start = (uint32_t *)(lds + ((a.d * 4 + 15) & ~15));  // [kMaxLists]
-    uint32_t *lst_cur = lst_start + kMaxLists;                         // [kMaxLists]
-    uint32_t *lst_end = lst_cur + kMaxLists;                           // [kMaxLists]
-    uint32_t *lst_pre = lst_end + kMaxLists;                           // [kMaxLists + 1]
-    uint32_t *lst_take = lst_pre + kMaxLists + 1;                      // [kMaxLists]
-    uint64_t *sbuf = (uint64_t *)(((uintptr_t)(lst_take + kMaxLists) + 15) & ~(uintptr_t)15); // [kSortCap]
+    uint32_t *lst_start = (uint32_t *)(lds + ((a.d * 4 + 15) & ~15));  // [nl]
+    uint32_t *lst_cur = lst_start + nlp;                               // [nl]
+    uint32_t *lst_end = lst_cur + nlp;                                 // [nl]
+    uint32_t *lst_pre = lst_end + nlp;                                 // [nl + 1]
+    uint32_t *lst_take = lst_pre + nlp;                                // [nl]
+    uint64_t *sbuf = (uint64_t *)(((uintptr_t)(lst_take + nlp) + 15) & ~(uintptr_t)15); // [kSortCap]
     uint64_t *topk = sbuf + kSortCap;                                  // [kMaxK]
     uint32_t *cand = (uint32_t *)(topk + kMaxK);                       // [kCap]
     __shared__ uint32_t red[QW];
@@ -587,11 +614,12 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(2))) void qu
                 }
             }
         };
-        using nrv = std::integral_constant<int, kScoreRowsV4>;
+        constexpr int NRV = QShape<QT>::nr;
+        using nrv = std::integral_constant<int, NRV>;
         using nr2 = std::integral_constant<int, 2>;
         if (a.vec4)
-            score_all(nrv{}, [&](const int64_t (&row)[kScoreRowsV4], float (&acc)[kScoreRowsV4], float (&xx)[kScoreRowsV4]) {
-                score_rows_v4<kScoreRowsV4>(a, qv, row, acc, xx);
+            score_all(nrv{}, [&](const int64_t (&row)[NRV], float (&acc)[NRV], float (&xx)[NRV]) {
+                score_rows_v4<NRV>(a, qv, row, acc, xx);
             });
         else if (a.bdt == LSH_F32)
             score_all(nr2{}, [&](const int64_t (&row)[2], float (&acc)[2], float (&xx)[2]) {
@@ -724,9 +752,10 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
     a.ids = ids;
     a.score = score;
     a.ncand = ncand;
-    size_t lds = (size_t)((Q->d * 4 + 15) & ~15) + (size_t)(5 * kMaxLists + 1) * 4 + 16 +
-                 (size_t)(kSortCap + kMaxK) * 8 + (size_t)kCap * 4;
     const bool solo = Q->n <= device_cu_count();
+    const int nl = nseg * a.L;
+    const size_t lds = solo ? query_lds_bytes<kQThreadsSolo>(Q->d, nl)
+                            : query_lds_bytes<kQThreads>(Q->d, nl);
     const void *fn = solo ? (const void *)query_kernel<kQThreadsSolo>
                           : (const void *)query_kernel<kQThreads>;
     LSH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
