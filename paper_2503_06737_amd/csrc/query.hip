@@ -380,6 +380,22 @@ __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *red)
     return t;
 }
 
+template <int QW>
+__device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t *red)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1)
+        v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
+    if (lane_id() == 0)
+        red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    uint32_t t = 0;
+    for (int w = 0; w < QW; ++w)
+        t = max(t, red[w]);
+    __syncthreads();
+    return t;
+}
+
 // Exclusive prefix of v over the block (thread order); *total gets the sum.
 template <int QW>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, uint32_t *total)
@@ -405,6 +421,124 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, u
     return off + incl - v;
 }
 
+constexpr int kWinBins = 256;
+
+// The bound of a window when the rem remaining (bucket, id) entries exceed
+// the capacity: with lo the smallest remaining id and [lo, hi] the range
+// still in question, a histogram of the remaining ids over kWinBins equal
+// parts of the range gives the largest part boundary below which at most
+// kCap entries lie.  If the first part alone holds more, the range narrows
+// to it and the count is repeated (at most four times: the part width falls
+// 256-fold each time, and one id value has at most nl <= kCap entries, one
+// per list, so a single-id part always fits).  Entries are spread over the
+// threads through the prefix of the lists' remaining counts (lst_pre /
+// lst_take, rewritten by the caller afterwards).
+template <int QT>
+__device__ void window_bound(const QueryArgs &a, int nl, uint32_t rem, const uint32_t *lst_cur,
+                             const uint32_t *lst_end, uint32_t *lst_pre, uint32_t *lst_take,
+                             uint32_t *hist, uint32_t *red, uint32_t *out)
+{
+    constexpr int QW = QT / kWave;
+    constexpr int kCap = QShape<QT>::cap;
+    const int tid = threadIdx.x;
+    // smallest and largest remaining id (each list ascends)
+    uint32_t mn = 0, mx = 0;
+    for (int li = tid; li < nl; li += QT) {
+        if (lst_cur[li] < lst_end[li]) {
+            const int sg = li / a.L, t = li % a.L;
+            const uint32_t *ids = a.seg[sg].ids + (int64_t)t * a.seg[sg].n;
+            mn = max(mn, ~ids[lst_cur[li]]);
+            mx = max(mx, ids[lst_end[li] - 1u]);
+        }
+        lst_take[li] = lst_end[li] - lst_cur[li];
+    }
+    const uint32_t lo = ~block_max_u32<QW>(mn, red);
+    uint32_t hi = block_max_u32<QW>(mx, red);
+    {
+        const int per = (nl + QT - 1) / QT;
+        const int l0 = tid * per, l1 = l0 + per < nl ? l0 + per : nl;
+        uint32_t mine = 0;
+        for (int li = l0; li < l1; ++li)
+            mine += lst_take[li];
+        uint32_t tot;
+        uint32_t run = block_excl_scan<QW>(mine, red, &tot);
+        for (int li = l0; li < l1; ++li) {
+            lst_pre[li] = run;
+            run += lst_take[li];
+        }
+    }
+    __syncthreads();
+    while (true) {
+        // parts of width wid (64-bit: the range may span all 2^32 ids)
+        const uint64_t span = (uint64_t)hi - lo + 1u;
+        const uint64_t wid = (span + kWinBins - 1) / kWinBins;
+        for (int i = tid; i < kWinBins; i += QT)
+            hist[i] = 0;
+        __syncthreads();
+        for (uint32_t e = tid; e < rem; e += QT) {
+            int l0 = 0, l1 = nl; // the list holding entry e: last li with pre[li] <= e
+            while (l1 - l0 > 1) {
+                const int mid = (l0 + l1) >> 1;
+                if (lst_pre[mid] <= e)
+                    l0 = mid;
+                else
+                    l1 = mid;
+            }
+            while (lst_take[l0] == 0 || lst_pre[l0] + lst_take[l0] <= e)
+                ++l0;
+            const int sg = l0 / a.L, t = l0 % a.L;
+            const uint32_t id =
+                a.seg[sg].ids[(int64_t)t * a.seg[sg].n + lst_cur[l0] + (e - lst_pre[l0])];
+            if (id <= hi)
+                atomicAdd(&hist[(uint32_t)(((uint64_t)id - lo) / wid)], 1u);
+        }
+        __syncthreads();
+        if (tid < kWave) {
+            // one wave scans the parts: lane l holds parts 4l .. 4l + 3
+            const int lane = lane_id();
+            uint32_t c[4], s4 = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                c[r] = hist[4 * lane + r];
+                s4 += c[r];
+            }
+            uint32_t incl = s4;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t u = __shfl_up(incl, o, kWave);
+                if (lane >= o)
+                    incl += u;
+            }
+            // parts b with (entries below part b) <= kCap: the largest is the bound
+            uint32_t run = incl - s4, best = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                run += c[r];
+                if (run <= (uint32_t)kCap)
+                    best = 4 * lane + r + 1;
+            }
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1)
+                best = max(best, (uint32_t)__shfl_xor((int)best, o, kWave));
+            if (lane == 0)
+                red[0] = best;
+        }
+        __syncthreads();
+        const uint32_t b = red[0];
+        __syncthreads();
+        if (b > 0) {
+            // ids below lo + b * wid: at most kCap entries, at least the first
+            // part's; never above hi + 1 (every counted id is at most hi, and
+            // ids stay below 2^32 - 1, so the bound is not the all-ids mark)
+            if (tid == 0)
+                *out = (uint32_t)min((uint64_t)lo + b * wid, (uint64_t)hi + 1u);
+            __syncthreads();
+            return;
+        }
+        hi = (uint32_t)((uint64_t)lo + wid - 1u); // the first part alone overflows: narrow to it
+    }
+}
+
 template <int QT>
 __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(QShape<QT>::wpe))) void
 query_kernel(QueryArgs a)
@@ -427,6 +561,7 @@ query_kernel(QueryArgs a)
     __shared__ float s_qnorm;
     __shared__ int s_kcur;
     __shared__ uint32_t s_ncand, s_hi, s_wcount, s_ucount;
+    __shared__ uint32_t s_hist[kWinBins];
 
     const int q = blockIdx.x;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
@@ -487,31 +622,13 @@ query_kernel(QueryArgs a)
         rem = block_sum_u32<QW>(rem, red);
         if (rem == 0)
             break;
-        // window [.., hi): all remaining if they fit, else the largest id bound
-        // whose entry count fits kCap (found by bisection on the id value)
+        // window [.., hi): all remaining if they fit, else an id bound whose
+        // entry count fits kCap, from histograms of the remaining entries' ids
         if (tid == 0)
             s_hi = 0xffffffffu;
         __syncthreads();
-        if (rem > kCap) {
-            uint32_t lo_v = 0, hi_v = 0xffffffffu; // count(lo_v) <= kCap < count(hi_v)
-            while (hi_v - lo_v > 1) {
-                uint32_t mid = lo_v + ((hi_v - lo_v) >> 1);
-                uint32_t c = 0;
-                for (int li = tid; li < nl; li += QT) {
-                    int sg = li / a.L, t = li % a.L;
-                    const uint32_t *ids = a.seg[sg].ids + (int64_t)t * a.seg[sg].n;
-                    c += lower_bound_u32(ids, lst_cur[li], lst_end[li], mid) - lst_cur[li];
-                }
-                c = block_sum_u32<QW>(c, red);
-                if (c <= kCap)
-                    lo_v = mid;
-                else
-                    hi_v = mid;
-            }
-            if (tid == 0)
-                s_hi = lo_v; // >= one id beyond the smallest remaining: progress
-            __syncthreads();
-        }
+        if (rem > kCap)
+            window_bound<QT>(a, nl, rem, lst_cur, lst_end, lst_pre, lst_take, s_hist, red, &s_hi);
         const uint32_t hiv = s_hi;
         for (int li = tid; li < nl; li += QT) {
             int sg = li / a.L, t = li % a.L;
