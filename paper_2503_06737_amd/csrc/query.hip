@@ -34,17 +34,18 @@ constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 
 
 // Per workgroup shape: cap, the (bucket, id) entries of a window; nr, the
 // FP32 candidate rows a wave scores together (their loads in flight at
-// once); wpe, the waves per SIMD the registers are sized for.  A solo query
+// once); wpe, the waves per SIMD the registers are sized for; sort_cpw, the
+// chunks of 256 keys a wave holds in registers when the block sorts.  A solo query
 // takes windows of 2048 entries and six rows per wave.  In a batch, windows
 // of 1024 entries, three rows per wave and at most 128 VGPRs leave the LDS
 // and registers for four queries per CU (two with the solo sizes), so more
 // queries overlap their latency-bound phases.
 template <int QT> struct QShape;
 template <> struct QShape<kQThreadsSolo> {
-    static constexpr int cap = 2048, nr = 6, wpe = 2;
+    static constexpr int cap = 2048, nr = 6, wpe = 2, sort_cpw = 2;
 };
 template <> struct QShape<kQThreads> {
-    static constexpr int cap = 1024, nr = 3, wpe = 4;
+    static constexpr int cap = 1024, nr = 3, wpe = 4, sort_cpw = 1;
 };
 template <int QT> constexpr int sort_cap() { return pow2_at_least(QShape<QT>::cap + kMaxK); }
 
@@ -280,28 +281,7 @@ __device__ __forceinline__ int64_t lower_bound_keys(const uint64_t *uk, int64_t 
     return hi;
 }
 
-// Bitonic sort of n (power of two) 64-bit keys in LDS, ascending, whole block.
-__device__ void block_bitonic(uint64_t *s, int n)
-{
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                int ixj = i ^ j;
-                if (ixj > i) {
-                    uint64_t x = s[i], y = s[ixj];
-                    bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        s[i] = y;
-                        s[ixj] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// The same sort by one wave in registers, for n <= 256 keys: element e =
+// Bitonic sort of n <= 256 keys in LDS by one wave in registers: element e =
 // 4 * lane + r is v[r] of the lane (keys past n sort last as ~0).  The
 // network always spans 256 elements; the steps with j >= 4 exchange with
 // lane ^ (j / 4), the others within the lane, and none needs a workgroup
@@ -352,15 +332,128 @@ __device__ __forceinline__ void wave_bitonic256(uint64_t *s, int n)
     }
 }
 
-// Ascending sort of n (a power of two) keys in LDS: the first wave alone
-// when n <= 256, else the whole block.  Every thread calls; ends with a
-// workgroup barrier.
+// Bitonic sort of n (power of two) 64-bit keys in LDS, ascending, whole
+// block, one workgroup barrier per step.
+__device__ void block_bitonic(uint64_t *s, int n)
+{
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t x = s[i], y = s[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        s[i] = y;
+                        s[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Bitonic sort of n keys (a power of two, 512 .. 256 * QW * CPW) in LDS by
+// the whole block with the keys in registers: wave w holds the chunks w,
+// w + QW, ... of 256 keys (key e = 256 chunk + 4 lane + r in v[c][r]).  The
+// compare-exchange steps of distance below 256 stay inside a chunk and run
+// in registers (lane exchanges for distances 4 .. 128, within the lane
+// below 4); only the steps of distance 256 and more pass through LDS, two
+// workgroup barriers each: 6 steps for 2048 keys and 10 for 4096, where the
+// plain network has 66 and 78 barriers.
+template <int QW, int CPW>
+__device__ void block_bitonic_regs(uint64_t *s, int n)
+{
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int nch = n >> 8;
+    uint64_t v[CPW][4];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const int ch = wid + c * QW;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            v[c][r] = ch < nch ? s[256 * ch + 4 * lane + r] : 0ull;
+    }
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 256) {
+#pragma unroll
+                for (int c = 0; c < CPW; ++c)
+                    if (wid + c * QW < nch) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            s[256 * (wid + c * QW) + 4 * lane + r] = v[c][r];
+                    }
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < CPW; ++c)
+                    if (wid + c * QW < nch) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int e = 256 * (wid + c * QW) + 4 * lane + r;
+                            const uint64_t y = s[e ^ j];
+                            const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+                            v[c][r] = keep_min == (y < v[c][r]) ? y : v[c][r];
+                        }
+                    }
+                __syncthreads();
+            } else if (j >= 4) {
+#pragma unroll
+                for (int c = 0; c < CPW; ++c)
+                    if (wid + c * QW < nch) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int e = 256 * (wid + c * QW) + 4 * lane + r;
+                            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v[c][r], j >> 2, kWave);
+                            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v[c][r] >> 32), j >> 2, kWave);
+                            const uint64_t y = ((uint64_t)hi << 32) | lo;
+                            const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+                            v[c][r] = keep_min == (y < v[c][r]) ? y : v[c][r];
+                        }
+                    }
+            } else {
+#pragma unroll
+                for (int c = 0; c < CPW; ++c)
+                    if (wid + c * QW < nch) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            if ((r & j) == 0) {
+                                const bool asc = ((256 * (wid + c * QW) + 4 * lane + r) & k) == 0;
+                                const uint64_t x = v[c][r], y = v[c][r | j];
+                                const bool swap = asc ? (y < x) : (x < y);
+                                v[c][r] = swap ? y : x;
+                                v[c][r | j] = swap ? x : y;
+                            }
+                        }
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+        if (wid + c * QW < nch) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                s[256 * (wid + c * QW) + 4 * lane + r] = v[c][r];
+        }
+    __syncthreads();
+}
+
+// Ascending sort of n (a power of two, at most 512 * QW) keys in LDS: the
+// first wave alone when n <= 256, else the whole block with the keys in
+// registers, CPW chunks of 256 per wave (the batch workgroup, short of
+// registers, holds one and sorts larger sets with one barrier per step).
+// Every thread calls; ends with a workgroup barrier.
+template <int QW, int CPW>
 __device__ __forceinline__ void sort_keys(uint64_t *s, int n)
 {
     if (n <= 4 * kWave) {
         if (threadIdx.x < kWave)
             wave_bitonic256(s, n);
         __syncthreads();
+    } else if (n <= 256 * QW * CPW) {
+        block_bitonic_regs<QW, CPW>(s, n);
     } else {
         block_bitonic(s, n);
     }
@@ -683,7 +776,7 @@ query_kernel(QueryArgs a)
         __syncthreads();
         for (int li = tid; li < nl; li += QT)
             lst_cur[li] += lst_take[li];
-        sort_keys(sbuf, p2);
+        sort_keys<QW, QShape<QT>::sort_cpw>(sbuf, p2);
         {
             // distinct ids, compacted in order: thread owns a contiguous run
             const int per = (p2 + QT - 1) / QT;
@@ -762,7 +855,7 @@ query_kernel(QueryArgs a)
                 sbuf[e] = e < tot ? topk[e - uc] : ~0ull;
         }
         __syncthreads();
-        sort_keys(sbuf, m2);
+        sort_keys<QW, QShape<QT>::sort_cpw>(sbuf, m2);
         int nk = tot < a.k ? tot : a.k;
         for (int e = tid; e < nk; e += QT)
             topk[e] = sbuf[e];
