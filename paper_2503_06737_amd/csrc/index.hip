@@ -122,6 +122,17 @@ __device__ __forceinline__ uint64_t compact_mask(uint64_t tor, uint64_t tand, in
     return vm && __popcll(vm) <= bits ? vm : 0ull;
 }
 
+// Table t is in (key, id) order once scattered when its segment digit holds
+// every varying key bit (at most B of them: the compacted digit) or no bit
+// varies: each segment is then one run of equal keys, in id order (the
+// scatter is stable).  Such a table is scattered straight to its final
+// buffers and skips the segment sorts and the big-segment path.
+__device__ __forceinline__ bool table_complete(const uint64_t *tor, const uint64_t *tand, int t,
+                                               int bits)
+{
+    return __popcll(tor[t] & ~tand[t]) <= bits;
+}
+
 __device__ __forceinline__ bool chunk_varies(uint64_t vm, int p)
 {
     return ((vm >> (8 * p)) & 255u) != 0;
@@ -404,7 +415,8 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
         a.ghist[(t << a.msd_bits) + d] = c;
     }
     uint32_t run = scan_excl(c, R, wsum);
-    const bool big = d < R && c > (uint32_t)kSegSmall;
+    const bool big = d < R && c > (uint32_t)kSegSmall &&
+                     !table_complete(a.tor, a.tand, t, a.msd_bits);
     const uint32_t ntl = big ? (c + kTile - 1) / kTile : 0u;
     const uint32_t bi = scan_excl(big ? 1u : 0u, R, wsum);
     const uint32_t ti = scan_excl(ntl, R, wsum);
@@ -694,8 +706,9 @@ msd_scatter_kernel(BuildArgs a)
         a.tile_hist + ((int64_t)t * a.ntiles + (int64_t)blockIdx.x * (kMsdTile / kTile)) * R;
     // one ballot per digit bit that can be set (B at most 8, 9 or 10)
     const uint64_t *kin = a.kin + (int64_t)t * a.key_ld + base;
-    uint64_t *ko = a.ka + (int64_t)t * a.n;
-    uint32_t *io = a.ia + (int64_t)t * a.n;
+    const bool done = table_complete(a.tor, a.tand, t, a.msd_bits);
+    uint64_t *ko = (done ? a.kb : a.ka) + (int64_t)t * a.n;
+    uint32_t *io = (done ? a.ids : a.ia) + (int64_t)t * a.n;
     const uint32_t id0 = a.id_base + (uint32_t)base;
     if (a.msd_bits <= 8)
         scatter_tile<kMsdRadixMax, kMsdItems, 8>(s, kin, nullptr, id0, cnt, shift, a.msd_bits,
@@ -951,7 +964,7 @@ __global__ __launch_bounds__(NT) void seg_sort_kernel(BuildArgs a)
         return;
     const int e = (t << a.msd_bits) + d;
     const int cnt = (int)a.ghist[e];
-    if (cnt <= LO || cnt > NT * kItems)
+    if (cnt <= LO || cnt > NT * kItems || table_complete(a.tor, a.tand, t, a.msd_bits))
         return;
     const int64_t base = (int64_t)t * a.n + a.seg_start[e];
     seg_sort_body<NT>(s, a.ka + base, a.ia + base, cnt, a.kb + base, a.ids + base);
