@@ -25,7 +25,9 @@
  *     space comes in through explicit workspace arguments whose size the
  *     matching *_bytes() function returns.
  *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
- *     default stream).  Nothing blocks except argument validation on the host.
+ *     default stream), and ordered on it (lsh_build_index runs part of its
+ *     kernels on a side stream that `stream` then waits for).  Nothing blocks
+ *     except argument validation on the host.
  *   - Return value: LSH_OK, or a negative lsh_status with a message available
  *     from lsh_last_error() (thread-local).  On LSH_EINVAL, LSH_ENOMEM and
  *     LSH_ERANGE nothing was enqueued.  LSH_EHIP means the runtime refused a
@@ -290,6 +292,11 @@ size_t lsh_build_workspace_bytes(int64_t n, int32_t L);
  * 256-byte aligned), ws: workspace (lsh_build_workspace_bytes, 256-byte
  * aligned; free for reuse once the enqueued work completes).  On success
  * *out receives a descriptor (release with lsh_index_free).
+ * When n > 4096 and `stream` is not capturing a graph, the heavy-bucket
+ * kernels run on a side stream of the device that the library creates on
+ * first use (default priority) and that `stream` waits for before the last
+ * kernel, so the build as a whole stays ordered on `stream`; builds from
+ * several host threads take the side stream one at a time.
  * ERANGE if id_base + n exceeds 2^32 - 1. */
 lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int64_t n, int32_t L,
                            int64_t id_base, void *mem, size_t mem_bytes, void *workspace,

@@ -34,6 +34,8 @@
 
 #include "lsh_internal.h"
 
+#include <mutex>
+
 namespace lsh {
 
 constexpr int kThreads = 1024;             // scatter / big-segment workgroups
@@ -1756,6 +1758,41 @@ WsLayout ws_layout(int64_t n, int32_t L)
     return w;
 }
 
+// The big-segment kernels of a build run on a side stream of the device,
+// concurrently with the segment sorts on the caller's stream: the two touch
+// disjoint segments of the sorted arrays, and the big-segment lists, pivots,
+// class counts and stacks are theirs alone.  The caller's stream waits for
+// the side stream before the run-head pass.  One side stream (default
+// priority, non-blocking) and one pair of events per device, created on
+// first use; a build enqueues its fork and join while holding the lock, so
+// the builds of several host threads take the side stream one at a time.
+constexpr int kMaxSideDevices = 64;
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+SideStream g_side[kMaxSideDevices];
+
+hipError_t side_stream(SideStream **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxSideDevices)
+        return hipErrorInvalidDevice;
+    SideStream &sd = g_side[dev];
+    if (!sd.s && (e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking)) != hipSuccess)
+        return e;
+    if (!sd.fork && (e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming)) != hipSuccess)
+        return e;
+    if (!sd.join && (e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming)) != hipSuccess)
+        return e;
+    *out = &sd;
+    return hipSuccess;
+}
+
 } // namespace
 
 extern "C" size_t lsh_index_bytes(int64_t n, int32_t L)
@@ -1887,6 +1924,29 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     constexpr int tpm = kMsdTile / kTile;
     hipLaunchKernelGGL(msd_scatter_kernel, dim3((wl.ntiles + tpm - 1) / tpm, L), dim3(kThreads),
                        scatter_lds, s, ba);
+    // Fork the big-segment path onto the side stream when a segment can
+    // exceed the segment sorts (n > kSegSmall) and the caller's stream is not
+    // being captured into a graph; otherwise everything runs on the caller's
+    // stream, in the same order.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) {
+        // (the legacy stream while another stream captures): no fork, and
+        // the error is cleared so that the launch check below does not see it
+        (void)hipGetLastError();
+        cap = hipStreamCaptureStatusActive;
+    }
+    std::unique_lock<std::mutex> side_lock(g_side_mu, std::defer_lock);
+    SideStream *side = nullptr;
+    hipStream_t sb = s;
+    if (n > kSegSmall && cap == hipStreamCaptureStatusNone) {
+        side_lock.lock();
+        if ((e = side_stream(&side)) != hipSuccess)
+            return fail("side stream", e);
+        if ((e = hipEventRecord(side->fork, s)) != hipSuccess ||
+            (e = hipStreamWaitEvent(side->s, side->fork, 0)) != hipSuccess)
+            return fail("side stream fork", e);
+        sb = side->s;
+    }
     hipLaunchKernelGGL((seg_sort_kernel<kSegThreadsS, 0>), dim3(1 << wl.bits, L),
                        dim3(kSegThreadsS), segs_lds, s, ba);
     hipLaunchKernelGGL((seg_sort_kernel<kSegThreads, kSegTiny>), dim3(1 << wl.bits, L),
@@ -1901,20 +1961,28 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     const int bg = (int)std::min<int64_t>(wl.big_grid, max_big);
     const int bt4 = (int)std::min<int64_t>(4 * wl.big_grid, max_bt);
     const int bt2 = (int)std::min<int64_t>(2 * wl.big_grid, max_bt);
-    hipLaunchKernelGGL(big_pivot_kernel, dim3(bg), dim3(kWave), 0, s, ba);
-    hipLaunchKernelGGL(big_count_kernel, dim3(bt4), dim3(256), 0, s, ba);
-    hipLaunchKernelGGL(big_cscan_kernel, dim3(bg), dim3(kWave), 0, s, ba);
-    hipLaunchKernelGGL(big_part_kernel, dim3(bt2), dim3(kThreads), 0, s, ba);
+    hipLaunchKernelGGL(big_pivot_kernel, dim3(bg), dim3(kWave), 0, sb, ba);
+    hipLaunchKernelGGL(big_count_kernel, dim3(bt4), dim3(256), 0, sb, ba);
+    hipLaunchKernelGGL(big_cscan_kernel, dim3(bg), dim3(kWave), 0, sb, ba);
+    hipLaunchKernelGGL(big_part_kernel, dim3(bt2), dim3(kThreads), 0, sb, ba);
     // the small parts of the split segments: as many workgroups as fit on
     // the 256 CUs at once (four and two per CU), at most two per big segment
     const int64_t parts = std::min<int64_t>(2 * nseg, 2 * max_big);
     hipLaunchKernelGGL((part_sort_kernel<kSegThreadsS, 0>),
                        dim3((int)std::min<int64_t>(parts, 4 * 256)), dim3(kSegThreadsS),
-                       segs_lds, s, ba);
+                       segs_lds, sb, ba);
     hipLaunchKernelGGL((part_sort_kernel<kSegThreads, 1>),
                        dim3((int)std::min<int64_t>(parts, 2 * 256)), dim3(kSegThreads), seg_lds,
-                       s, ba);
-    hipLaunchKernelGGL(big_sort_kernel, dim3(bg), dim3(kThreads), big_lds, s, ba);
+                       sb, ba);
+    hipLaunchKernelGGL(big_sort_kernel, dim3(bg), dim3(kThreads), big_lds, sb, ba);
+    if (side) {
+        if ((e = hipGetLastError()) != hipSuccess)
+            return fail("index kernels", e);
+        if ((e = hipEventRecord(side->join, sb)) != hipSuccess ||
+            (e = hipStreamWaitEvent(s, side->join, 0)) != hipSuccess)
+            return fail("side stream join", e);
+        side_lock.unlock();
+    }
 
     HeadArgs ha;
     ha.sk = ba.kb;

@@ -232,3 +232,61 @@ def test_sparse_image_rows_index_from_oracle_keys():
     b = synth.shifts(K * L, wl.w, wl.seed + 1)
     keys = oracle.hash_points(x, oracle.E2LSH, K, L, kind="cs", w=wl.w, b=b, h=h, s=s)["keys"]
     _check(keys)
+
+
+def test_builds_on_two_streams_and_threads_read_back_on_their_own_stream():
+    """Heavy buckets send segments to the big-segment kernels, which run on
+    the library's side stream.  Two host threads build on two non-default
+    streams at once; each reads its index back with copies enqueued on its
+    own stream only (no device-wide synchronisation), so the copies see the
+    side stream's results only if that stream waits for them.  Both indexes
+    equal the oracle's on every repetition."""
+    import threading
+    import torch
+    g = _rng(21)
+    n = 60000
+    sets = []
+    for i in range(2):
+        keys = g.integers(0, 2**63, (4, n), dtype=np.int64).astype(np.uint64) * np.uint64(2) + np.uint64(1)
+        heavy = g.random((4, n)) < 0.3
+        keys[heavy] = np.uint64(0x8123456789ABCDEF) + np.uint64(2 * i)
+        keys[1][g.random(n) < 0.2] = np.uint64(0x55) << np.uint64(56)
+        sets.append(keys)
+    refs = [oracle.build_index(k, 7) for k in sets]
+    d = dev()
+    kd = [to_dev(k) for k in sets]
+    torch.cuda.synchronize()
+    got = [[], []]
+    errs = []
+
+    def run(i):
+        try:
+            st = torch.cuda.Stream(d)
+            with torch.cuda.stream(st):
+                for _ in range(3):
+                    idx = lsh.lsh_build_index(kd[i], id_base=7)
+                    sid, uk, of, nu = idx.arrays()
+                    got[i].append((sid.to("cpu"), uk.to("cpu"), of.to("cpu"), nu.to("cpu"),
+                                   idx.check()))
+        except Exception as e:  # surfaced in the main thread
+            errs.append(e)
+
+    ths = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    assert not errs, errs
+    for i in range(2):
+        ref = refs[i]
+        assert len(got[i]) == 3
+        for sid, uk, of, nu, chk in got[i]:
+            assert chk == (0, 0)
+            nu = nu.numpy()
+            assert nu.tolist() == ref["nuniq"].tolist()
+            assert (sid.numpy().view(np.uint32) == ref["sorted_ids"]).all()
+            uk, of = uk.numpy().view(np.uint64), of.numpy().view(np.uint32)
+            for t in range(4):
+                u = int(nu[t])
+                assert (uk[t, :u] == ref["ukeys"][t, :u]).all()
+                assert (of[t, :u + 1] == ref["offs"][t, :u + 1]).all()
