@@ -49,6 +49,9 @@ constexpr int kRadix = 256;                // 8-bit digits below the segment dig
 // several counted tiles at once; one measured fastest)
 constexpr int kMsdItems = kItems;
 constexpr int kMsdTile = kThreads * kMsdItems;
+// Workgroups of a launch are dealt to the 8 XCDs (each with its own L2) in
+// turn: workgroup i runs on XCD i % 8.
+constexpr int kXcds = 8;
 constexpr int kSegThreads = 512;
 constexpr int kSegSmall = kSegThreads * kItems; // 4096: segments sorted by kSegThreads
 // segments of at most 2048 keys take a 256-thread workgroup with half the
@@ -696,16 +699,27 @@ msd_scatter_kernel(BuildArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     ScatterLds<kMsdRadixMax, kMsdItems> &s = *(ScatterLds<kMsdRadixMax, kMsdItems> *)lds;
-    const int t = blockIdx.y;
+    // Each XCD takes a contiguous range of the (table, tile) pairs in table
+    // order: consecutive tiles of a table write adjacent runs of every
+    // segment, and on one XCD the cache lines those runs share are completed
+    // in its L2 rather than written back in parts by two.
+    const int64_t ntm = (a.n + kMsdTile - 1) / kMsdTile;
+    const int64_t npair = ntm * a.L;
+    const int64_t chunk = (npair + kXcds - 1) / kXcds;
+    const int64_t pair = (int64_t)(blockIdx.x % kXcds) * chunk + (int64_t)(blockIdx.x / kXcds);
+    if (pair >= npair)
+        return;
+    const int t = (int)(pair / ntm);
+    const int64_t tile = pair % ntm;
     const int R = 1 << a.msd_bits;
     const int shift = top_shift(a.tor[t] & ~a.tand[t], a.msd_bits);
     const uint64_t cmask = compact_mask(a.tor[t], a.tand[t], a.msd_bits);
     // kMsdTile / kTile counted tiles at once: their run of a digit starts
     // where the first tile's run starts and covers the others
-    const int64_t base = (int64_t)blockIdx.x * kMsdTile;
+    const int64_t base = (int64_t)tile * kMsdTile;
     const int cnt = (int)min((int64_t)kMsdTile, a.n - base);
     const uint32_t *goff =
-        a.tile_hist + ((int64_t)t * a.ntiles + (int64_t)blockIdx.x * (kMsdTile / kTile)) * R;
+        a.tile_hist + ((int64_t)t * a.ntiles + (int64_t)tile * (kMsdTile / kTile)) * R;
     // one ballot per digit bit that can be set (B at most 8, 9 or 10)
     const uint64_t *kin = a.kin + (int64_t)t * a.key_ld + base;
     const bool done = table_complete(a.tor, a.tand, t, a.msd_bits);
@@ -1218,13 +1232,18 @@ __device__ __noinline__ void partition3(uint32_t (*cls)[4], const uint64_t *kin,
 }
 
 // Per tile of a big segment with a pivot: the stable 3-way scatter from
-// ka / ia to kb / ids (the == run lands in its final place).
+// ka / ia to kb / ids (the == run lands in its final place).  Each XCD takes
+// a contiguous range of the tile list (the grid is a multiple of kXcds), so
+// that consecutive tiles of a segment, which write adjacent ranges of each
+// class, share their boundary cache lines in one L2.
 __global__ __launch_bounds__(kThreads) void big_part_kernel(BuildArgs a)
 {
     __shared__ uint32_t cls[kWaves][4];
     __shared__ uint32_t base[4];
     const uint32_t nt = a.bcount[2];
-    for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
+    const uint32_t chunk = (nt + kXcds - 1) / kXcds;
+    const uint32_t j0 = (blockIdx.x % kXcds) * chunk, j1 = min(nt, j0 + chunk);
+    for (uint32_t j = j0 + blockIdx.x / kXcds; j < j1; j += gridDim.x / kXcds) {
         const uint32_t bi = a.btile[2 * j], k = a.btile[2 * j + 1];
         const uint32_t *b = a.blist + kBig * bi;
         if (!b[4])
@@ -1922,8 +1941,9 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     hipLaunchKernelGGL(msd_up_kernel, tiles, dim3(kThreads), 0, s, ba);
     hipLaunchKernelGGL(msd_scan_kernel, dim3(L), dim3(kMsdRadixMax), 0, s, ba);
     constexpr int tpm = kMsdTile / kTile;
-    hipLaunchKernelGGL(msd_scatter_kernel, dim3((wl.ntiles + tpm - 1) / tpm, L), dim3(kThreads),
-                       scatter_lds, s, ba);
+    const int64_t npair = (int64_t)((wl.ntiles + tpm - 1) / tpm) * L;
+    hipLaunchKernelGGL(msd_scatter_kernel, dim3((unsigned)((npair + kXcds - 1) / kXcds * kXcds)),
+                       dim3(kThreads), scatter_lds, s, ba);
     // Fork the big-segment path onto the side stream when a segment can
     // exceed the segment sorts (n > kSegSmall) and the caller's stream is not
     // being captured into a graph; otherwise everything runs on the caller's
@@ -1964,7 +1984,8 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     hipLaunchKernelGGL(big_pivot_kernel, dim3(bg), dim3(kWave), 0, sb, ba);
     hipLaunchKernelGGL(big_count_kernel, dim3(bt4), dim3(256), 0, sb, ba);
     hipLaunchKernelGGL(big_cscan_kernel, dim3(bg), dim3(kWave), 0, sb, ba);
-    hipLaunchKernelGGL(big_part_kernel, dim3(bt2), dim3(kThreads), 0, sb, ba);
+    hipLaunchKernelGGL(big_part_kernel, dim3((bt2 + kXcds - 1) / kXcds * kXcds), dim3(kThreads), 0,
+                       sb, ba);
     // the small parts of the split segments: as many workgroups as fit on
     // the 256 CUs at once (four and two per CU), at most two per big segment
     const int64_t parts = std::min<int64_t>(2 * nseg, 2 * max_big);
