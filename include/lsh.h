@@ -25,7 +25,10 @@
  *     space comes in through explicit workspace arguments whose size the
  *     matching *_bytes() function returns.
  *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
- *     default stream), and ordered on it (lsh_build_index runs part of its
+ *     default stream), which belongs to the current device (hipGetDevice;
+ *     lsh_build_index and lsh_hash_cs_noalloc with the recheck return
+ *     LSH_EINVAL otherwise, since their per-device state is the current
+ *     device's), and ordered on it (lsh_build_index runs part of its
  *     kernels on a side stream that `stream` then waits for).  Nothing blocks
  *     except argument validation on the host.
  *   - Return value: LSH_OK, or a negative lsh_status with a message available

@@ -1712,7 +1712,9 @@ extern "C" lsh_status lsh_hash_cs_noalloc(const lsh_points *pts, const uint32_t 
         if (wsb > lsh::kScratchBytes)
             LSH_FAIL(LSH_EINVAL, "recheck needs %zu bytes of scratch, the static array holds %zu",
                      wsb, lsh::kScratchBytes);
-        lsh_status st = lsh::scratch_ptr(&ws);
+        lsh_status st = lsh::check_stream_device(stream);
+        if (st == LSH_OK)
+            st = lsh::scratch_ptr(&ws);
         if (st != LSH_OK)
             return st;
     }

@@ -1850,6 +1850,8 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
         LSH_FAIL(LSH_EINVAL, "keys is NULL");
     IndexLayout il = index_layout(n, L);
     WsLayout wl = ws_layout(n, L);
+    if (lsh_status st = check_stream_device(stream); st != LSH_OK)
+        return st;
     if (!mem || mem_bytes < il.total || ((uintptr_t)mem & 255))
         LSH_FAIL(LSH_ENOMEM, "index memory needs %zu bytes (256-aligned), got %zu", il.total,
                  mem_bytes);

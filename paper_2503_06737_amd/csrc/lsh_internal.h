@@ -39,6 +39,10 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
+// LSH_OK when `stream` (NULL: the default stream) belongs to the current
+// device, else LSH_EINVAL: per-device state (the static scratch array, the
+// side stream of the index build) is that of the current device.
+lsh_status check_stream_device(void *stream);
 
 // Argument checks shared by the entry points (set the error message).
 lsh_status check_points(const lsh_points *p);

@@ -34,6 +34,18 @@ int device_cu_count()
     return cache[dev];
 }
 
+lsh_status check_stream_device(void *stream)
+{
+    if (!stream)
+        return LSH_OK;
+    int cur = 0, sd = 0;
+    LSH_HIP(hipGetDevice(&cur));
+    LSH_HIP(hipStreamGetDevice((hipStream_t)stream, &sd));
+    if (sd != cur)
+        LSH_FAIL(LSH_EINVAL, "the stream belongs to device %d but device %d is current", sd, cur);
+    return LSH_OK;
+}
+
 } // namespace lsh
 
 extern "C" const char *lsh_last_error(void) { return lsh::g_err; }
