@@ -147,9 +147,12 @@ def main():
         lsh._check(rc)
 
     index_holder = {}
+    # the build's heavy-bucket kernels run on a second stream, concurrently
+    # with its segment sorts (the call joins it back to the current stream)
+    side = torch.cuda.Stream(dev)
 
     def build():
-        idx = lsh.lsh_build_index(keys, mem=mem, ws=ws)
+        idx = lsh.lsh_build_index(keys, mem=mem, ws=ws, side_stream=side)
         index_holder["idx"] = idx
 
     def step(family=0, dense=False):

@@ -28,8 +28,8 @@
  *     default stream), which belongs to the current device (hipGetDevice;
  *     lsh_build_index and lsh_hash_cs_noalloc with the recheck return
  *     LSH_EINVAL otherwise, since their per-device state is the current
- *     device's), and ordered on it (lsh_build_index runs part of its
- *     kernels on a side stream that `stream` then waits for).  Nothing blocks
+ *     device's), and ordered on it (lsh_build_index may also use a second
+ *     stream the caller gives it, joined back to `stream`).  Nothing blocks
  *     except argument validation on the host.
  *   - Return value: LSH_OK, or a negative lsh_status with a message available
  *     from lsh_last_error() (thread-local).  On LSH_EINVAL, LSH_ENOMEM and
@@ -295,15 +295,17 @@ size_t lsh_build_workspace_bytes(int64_t n, int32_t L);
  * 256-byte aligned), ws: workspace (lsh_build_workspace_bytes, 256-byte
  * aligned; free for reuse once the enqueued work completes).  On success
  * *out receives a descriptor (release with lsh_index_free).
- * When n > 4096 and `stream` is not capturing a graph, the heavy-bucket
- * kernels run on a side stream of the device that the library creates on
- * first use (default priority) and that `stream` waits for before the last
- * kernel, so the build as a whole stays ordered on `stream`; builds from
- * several host threads take the side stream one at a time.
+ * side_stream: NULL, or a second stream of the same device.  Given one
+ * (other than `stream`), a build of more than 4096 points whose `stream` is
+ * not capturing a graph runs its heavy-bucket kernels there, concurrently
+ * with the segment sorts, and `stream` waits for them before the last
+ * kernel: the build as a whole stays ordered on `stream`, and work enqueued
+ * on side_stream before the call runs before those kernels.  The fork and
+ * join use a pair of events of the library per device, taken under a lock.
  * ERANGE if id_base + n exceeds 2^32 - 1. */
 lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int64_t n, int32_t L,
                            int64_t id_base, void *mem, size_t mem_bytes, void *workspace,
-                           size_t ws_bytes, lsh_index **out, void *stream);
+                           size_t ws_bytes, lsh_index **out, void *stream, void *side_stream);
 
 /* Fill *view with the device arrays of idx (host call, no GPU work). */
 lsh_status lsh_index_get_view(const lsh_index *idx, lsh_index_view *view);

@@ -1777,38 +1777,35 @@ WsLayout ws_layout(int64_t n, int32_t L)
     return w;
 }
 
-// The big-segment kernels of a build run on a side stream of the device,
-// concurrently with the segment sorts on the caller's stream: the two touch
+// A build given a side stream runs its big-segment kernels there,
+// concurrently with the segment sorts on its main stream: the two touch
 // disjoint segments of the sorted arrays, and the big-segment lists, pivots,
-// class counts and stacks are theirs alone.  The caller's stream waits for
-// the side stream before the run-head pass.  One side stream (default
-// priority, non-blocking) and one pair of events per device, created on
-// first use; a build enqueues its fork and join while holding the lock, so
-// the builds of several host threads take the side stream one at a time.
-constexpr int kMaxSideDevices = 64;
-struct SideStream {
-    hipStream_t s = nullptr;
+// class counts and stacks are theirs alone.  The main stream waits for the
+// side stream before the run-head pass.  The fork and join events are the
+// library's, one pair per device, created on first use; a build records and
+// waits on them while holding the lock, so that concurrent builds do not mix
+// their records.
+constexpr int kMaxForkDevices = 64;
+struct ForkEvents {
     hipEvent_t fork = nullptr, join = nullptr;
 };
-std::mutex g_side_mu;
-SideStream g_side[kMaxSideDevices];
+std::mutex g_fork_mu;
+ForkEvents g_fork[kMaxForkDevices];
 
-hipError_t side_stream(SideStream **out)
+hipError_t fork_events(ForkEvents **out)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)
         return e;
-    if (dev < 0 || dev >= kMaxSideDevices)
+    if (dev < 0 || dev >= kMaxForkDevices)
         return hipErrorInvalidDevice;
-    SideStream &sd = g_side[dev];
-    if (!sd.s && (e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking)) != hipSuccess)
+    ForkEvents &fe = g_fork[dev];
+    if (!fe.fork && (e = hipEventCreateWithFlags(&fe.fork, hipEventDisableTiming)) != hipSuccess)
         return e;
-    if (!sd.fork && (e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming)) != hipSuccess)
+    if (!fe.join && (e = hipEventCreateWithFlags(&fe.join, hipEventDisableTiming)) != hipSuccess)
         return e;
-    if (!sd.join && (e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming)) != hipSuccess)
-        return e;
-    *out = &sd;
+    *out = &fe;
     return hipSuccess;
 }
 
@@ -1830,7 +1827,8 @@ extern "C" size_t lsh_build_workspace_bytes(int64_t n, int32_t L)
 
 extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int64_t n, int32_t L,
                                       int64_t id_base, void *mem, size_t mem_bytes, void *ws,
-                                      size_t ws_bytes, lsh_index **out, void *stream)
+                                      size_t ws_bytes, lsh_index **out, void *stream,
+                                      void *side_stream)
 {
     using namespace lsh;
     if (!out)
@@ -1852,6 +1850,9 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     WsLayout wl = ws_layout(n, L);
     if (lsh_status st = check_stream_device(stream); st != LSH_OK)
         return st;
+    if (side_stream)
+        if (lsh_status st = check_stream_device(side_stream); st != LSH_OK)
+            return st;
     if (!mem || mem_bytes < il.total || ((uintptr_t)mem & 255))
         LSH_FAIL(LSH_ENOMEM, "index memory needs %zu bytes (256-aligned), got %zu", il.total,
                  mem_bytes);
@@ -1946,28 +1947,29 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     const int64_t npair = (int64_t)((wl.ntiles + tpm - 1) / tpm) * L;
     hipLaunchKernelGGL(msd_scatter_kernel, dim3((unsigned)((npair + kXcds - 1) / kXcds * kXcds)),
                        dim3(kThreads), scatter_lds, s, ba);
-    // Fork the big-segment path onto the side stream when a segment can
-    // exceed the segment sorts (n > kSegSmall) and the caller's stream is not
-    // being captured into a graph; otherwise everything runs on the caller's
-    // stream, in the same order.
+    // Fork the big-segment path onto the side stream when one is given, a
+    // segment can exceed the segment sorts (n > kSegSmall) and the main stream
+    // is not being captured into a graph; otherwise everything runs on the
+    // main stream, in the same order.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) != hipSuccess) {
+    if (side_stream && hipStreamIsCapturing(s, &cap) != hipSuccess) {
         // (the legacy stream while another stream captures): no fork, and
         // the error is cleared so that the launch check below does not see it
         (void)hipGetLastError();
         cap = hipStreamCaptureStatusActive;
     }
-    std::unique_lock<std::mutex> side_lock(g_side_mu, std::defer_lock);
-    SideStream *side = nullptr;
+    std::unique_lock<std::mutex> fork_lock(g_fork_mu, std::defer_lock);
+    ForkEvents *fe = nullptr;
     hipStream_t sb = s;
-    if (n > kSegSmall && cap == hipStreamCaptureStatusNone) {
-        side_lock.lock();
-        if ((e = side_stream(&side)) != hipSuccess)
-            return fail("side stream", e);
-        if ((e = hipEventRecord(side->fork, s)) != hipSuccess ||
-            (e = hipStreamWaitEvent(side->s, side->fork, 0)) != hipSuccess)
+    if (side_stream && (hipStream_t)side_stream != s && n > kSegSmall &&
+        cap == hipStreamCaptureStatusNone) {
+        fork_lock.lock();
+        if ((e = fork_events(&fe)) != hipSuccess)
+            return fail("fork events", e);
+        sb = (hipStream_t)side_stream;
+        if ((e = hipEventRecord(fe->fork, s)) != hipSuccess ||
+            (e = hipStreamWaitEvent(sb, fe->fork, 0)) != hipSuccess)
             return fail("side stream fork", e);
-        sb = side->s;
     }
     hipLaunchKernelGGL((seg_sort_kernel<kSegThreadsS, 0>), dim3(1 << wl.bits, L),
                        dim3(kSegThreadsS), segs_lds, s, ba);
@@ -1998,13 +2000,13 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
                        dim3((int)std::min<int64_t>(parts, 2 * 256)), dim3(kSegThreads), seg_lds,
                        sb, ba);
     hipLaunchKernelGGL(big_sort_kernel, dim3(bg), dim3(kThreads), big_lds, sb, ba);
-    if (side) {
+    if (fe) {
         if ((e = hipGetLastError()) != hipSuccess)
             return fail("index kernels", e);
-        if ((e = hipEventRecord(side->join, sb)) != hipSuccess ||
-            (e = hipStreamWaitEvent(s, side->join, 0)) != hipSuccess)
+        if ((e = hipEventRecord(fe->join, sb)) != hipSuccess ||
+            (e = hipStreamWaitEvent(s, fe->join, 0)) != hipSuccess)
             return fail("side stream join", e);
-        side_lock.unlock();
+        fork_lock.unlock();
     }
 
     HeadArgs ha;

@@ -80,7 +80,7 @@ def lib() -> C.CDLL:
         L.lsh_index_bytes.restype = sz
         L.lsh_build_workspace_bytes.argtypes = [i64, i32]
         L.lsh_build_workspace_bytes.restype = sz
-        L.lsh_build_index.argtypes = [vp, i64, i64, i32, i64, vp, sz, vp, sz, vp, vp]
+        L.lsh_build_index.argtypes = [vp, i64, i64, i32, i64, vp, sz, vp, sz, vp, vp, vp]
         L.lsh_index_get_view.argtypes = [vp, vp]
         L.lsh_index_free.argtypes = [vp]
         L.lsh_index_free.restype = None
@@ -321,8 +321,11 @@ class Index:
 
 
 def lsh_build_index(keys: torch.Tensor, id_base: int = 0, mem: torch.Tensor | None = None,
-                    ws: torch.Tensor | None = None) -> Index:
-    """Bucket the points of every table.  keys: [L][n] (int64 bit patterns of u64 keys)."""
+                    ws: torch.Tensor | None = None,
+                    side_stream: torch.cuda.Stream | None = None) -> Index:
+    """Bucket the points of every table.  keys: [L][n] (int64 bit patterns of u64 keys).
+    side_stream: a second stream for the heavy-bucket kernels (joined back to
+    the current stream), or None to run the whole build on the current stream."""
     L, n = keys.shape
     ib = lib().lsh_index_bytes(n, L)
     wb = lib().lsh_build_workspace_bytes(n, L)
@@ -333,7 +336,8 @@ def lsh_build_index(keys: torch.Tensor, id_base: int = 0, mem: torch.Tensor | No
     h = C.c_void_p()
     _check(lib().lsh_build_index(_ptr(keys) if n else None, keys.stride(0) if n else 0, n, L,
                                  id_base, _ptr(mem), mem.numel(), _ptr(ws), ws.numel(),
-                                 C.byref(h), _stream()))
+                                 C.byref(h), _stream(),
+                                 None if side_stream is None else C.c_void_p(side_stream.cuda_stream)))
     return Index(h, mem, n, L, id_base, ws)
 
 

@@ -50,6 +50,6 @@ def test_library_argument_errors_need_no_gpu():
     assert st == -1 and b"m = K*L" in L.lsh_last_error()
     h = C.c_void_p()
     st = L.lsh_build_index(C.c_void_p(256), 0, 10, 2, (1 << 32) - 5, C.c_void_p(256), 1 << 20,
-                           C.c_void_p(256), 1 << 20, C.byref(h), None)
+                           C.c_void_p(256), 1 << 20, C.byref(h), None, None)
     assert st == -5
     assert L.lsh_index_bytes(1000, 4) >= 1000 * 4 * 16

@@ -11,20 +11,25 @@ pytestmark = pytest.mark.gpu
 
 
 def _check(keys, id_base=0):
+    """Build on the current stream alone, then with the heavy-bucket kernels
+    on a side stream; both indexes equal the oracle's."""
+    import torch
     ref = oracle.build_index(keys, id_base)
-    idx = lsh.lsh_build_index(to_dev(keys), id_base=id_base)
-    assert idx.check() == (0, 0)
-    sid, uk, of, nu = idx.arrays()
-    L, n = keys.shape
-    nu = to_host(nu)
-    assert nu.tolist() == ref["nuniq"].tolist()
-    sid = to_host(sid, np.uint32)
-    assert (sid == ref["sorted_ids"]).all()
-    uk, of = to_host(uk, np.uint64), to_host(of, np.uint32)
-    for t in range(L):
-        u = int(nu[t])
-        assert (uk[t, :u] == ref["ukeys"][t, :u]).all()
-        assert (of[t, :u + 1] == ref["offs"][t, :u + 1]).all()
+    kd = to_dev(keys)
+    for side in (None, torch.cuda.Stream(dev())):
+        idx = lsh.lsh_build_index(kd, id_base=id_base, side_stream=side)
+        assert idx.check() == (0, 0)
+        sid, uk, of, nu = idx.arrays()
+        L, n = keys.shape
+        nu = to_host(nu)
+        assert nu.tolist() == ref["nuniq"].tolist()
+        sid = to_host(sid, np.uint32)
+        assert (sid == ref["sorted_ids"]).all()
+        uk, of = to_host(uk, np.uint64), to_host(of, np.uint32)
+        for t in range(L):
+            u = int(nu[t])
+            assert (uk[t, :u] == ref["ukeys"][t, :u]).all()
+            assert (of[t, :u + 1] == ref["offs"][t, :u + 1]).all()
     return idx
 
 
@@ -236,11 +241,12 @@ def test_sparse_image_rows_index_from_oracle_keys():
 
 def test_builds_on_two_streams_and_threads_read_back_on_their_own_stream():
     """Heavy buckets send segments to the big-segment kernels, which run on
-    the library's side stream.  Two host threads build on two non-default
-    streams at once; each reads its index back with copies enqueued on its
-    own stream only (no device-wide synchronisation), so the copies see the
-    side stream's results only if that stream waits for them.  Both indexes
-    equal the oracle's on every repetition."""
+    the side stream the build is given.  Two host threads build at once, each
+    on a non-default stream with a side stream of its own; each reads its
+    index back with copies enqueued on its main stream only (no device-wide
+    synchronisation), so the copies see the side stream's results only if
+    the main stream waits for them.  Both indexes equal the oracle's on every
+    repetition."""
     import threading
     import torch
     g = _rng(21)
@@ -261,10 +267,10 @@ def test_builds_on_two_streams_and_threads_read_back_on_their_own_stream():
 
     def run(i):
         try:
-            st = torch.cuda.Stream(d)
+            st, side = torch.cuda.Stream(d), torch.cuda.Stream(d)
             with torch.cuda.stream(st):
                 for _ in range(3):
-                    idx = lsh.lsh_build_index(kd[i], id_base=7)
+                    idx = lsh.lsh_build_index(kd[i], id_base=7, side_stream=side)
                     sid, uk, of, nu = idx.arrays()
                     got[i].append((sid.to("cpu"), uk.to("cpu"), of.to("cpu"), nu.to("cpu"),
                                    idx.check()))
