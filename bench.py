@@ -106,6 +106,16 @@ def main():
                           "(the multi-GPU design shards points and is not built)"}))
         sys.exit(2)
 
+    # One hardware queue per stream this run keeps busy at once: the null
+    # stream, the build's side stream, and serving's insert and two query
+    # streams.  With HIP's default of four, a stream used before serving
+    # starts leaves two of serving's streams on one in-order queue, where one
+    # waits behind the other's kernels: the overload stream lost 30% of its
+    # throughput.  Read when HIP initialises, so it is set before torch is
+    # imported.
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+        os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
     import torch
     from paper_2503_06737_amd import lsh, synth
 

@@ -25,7 +25,10 @@ and insert requests arrive over time, and every kernel is a library call
   wait on an event recorded after the latest insert, so they see every point
   that arrived before them.  Batches on different streams overlap on the
   device: one batch's re-rank runs beside the next batch's hashing and
-  index build.
+  index build.  They overlap only on hardware queues of their own: a process
+  gets GPU_MAX_HW_QUEUES of them (HIP's default is 4), bound to streams as
+  they are first used, so a process that also keeps other streams busy
+  should raise it (bench.py sets 8).
 * A query sees exactly the inserts that arrived before it (its watermark).
   Queries of one batch are grouped by watermark, one `lsh_query` call per
   group, so a result never depends on how requests were batched.
