@@ -297,9 +297,9 @@ size_t lsh_build_workspace_bytes(int64_t n, int32_t L);
  * *out receives a descriptor (release with lsh_index_free).
  * side_stream: NULL, or a second stream of the same device.  Given one
  * (other than `stream`), a build of more than 4096 points whose `stream` is
- * not capturing a graph runs its heavy-bucket kernels there, concurrently
- * with the segment sorts, and `stream` waits for them before the last
- * kernel: the build as a whole stays ordered on `stream`, and work enqueued
+ * not capturing a graph runs its heavy-bucket split and sort there,
+ * concurrently with the segment sorts, and `stream` waits for them before the
+ * last kernel: the build as a whole stays ordered on `stream`, and work enqueued
  * on side_stream before the call runs before those kernels.  The fork and
  * join use a pair of events of the library per device, taken under a lock.
  * ERANGE if id_base + n exceeds 2^32 - 1. */

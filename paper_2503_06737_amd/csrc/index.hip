@@ -1777,17 +1777,18 @@ WsLayout ws_layout(int64_t n, int32_t L)
     return w;
 }
 
-// A build given a side stream runs its big-segment kernels there,
+// A build given a side stream runs its big-segment split and sort there,
 // concurrently with the segment sorts on its main stream: the two touch
 // disjoint segments of the sorted arrays, and the big-segment lists, pivots,
-// class counts and stacks are theirs alone.  The main stream waits for the
-// side stream before the run-head pass.  The fork and join events are the
+// class counts and stacks are theirs alone.  The main stream sorts the
+// split's small parts after its segment sorts, once the side stream has
+// partitioned them, and waits for the side stream before the run-head pass.  The fork and join events are the
 // library's, one pair per device, created on first use; a build records and
 // waits on them while holding the lock, so that concurrent builds do not mix
 // their records.
 constexpr int kMaxForkDevices = 64;
 struct ForkEvents {
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t fork = nullptr, parted = nullptr, join = nullptr;
 };
 std::mutex g_fork_mu;
 ForkEvents g_fork[kMaxForkDevices];
@@ -1804,6 +1805,9 @@ hipError_t fork_events(ForkEvents **out)
     if (!fe.fork && (e = hipEventCreateWithFlags(&fe.fork, hipEventDisableTiming)) != hipSuccess)
         return e;
     if (!fe.join && (e = hipEventCreateWithFlags(&fe.join, hipEventDisableTiming)) != hipSuccess)
+        return e;
+    if (!fe.parted &&
+        (e = hipEventCreateWithFlags(&fe.parted, hipEventDisableTiming)) != hipSuccess)
         return e;
     *out = &fe;
     return hipSuccess;
@@ -1990,15 +1994,20 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     hipLaunchKernelGGL(big_cscan_kernel, dim3(bg), dim3(kWave), 0, sb, ba);
     hipLaunchKernelGGL(big_part_kernel, dim3((bt2 + kXcds - 1) / kXcds * kXcds), dim3(kThreads), 0,
                        sb, ba);
+    // the small parts are sorted on the main stream once the partition is
+    // done (after the segment sorts there), the big sort on the side stream
+    if (fe && ((e = hipEventRecord(fe->parted, sb)) != hipSuccess ||
+               (e = hipStreamWaitEvent(s, fe->parted, 0)) != hipSuccess))
+        return fail("side stream partition event", e);
     // the small parts of the split segments: as many workgroups as fit on
     // the 256 CUs at once (four and two per CU), at most two per big segment
     const int64_t parts = std::min<int64_t>(2 * nseg, 2 * max_big);
     hipLaunchKernelGGL((part_sort_kernel<kSegThreadsS, 0>),
                        dim3((int)std::min<int64_t>(parts, 4 * 256)), dim3(kSegThreadsS),
-                       segs_lds, sb, ba);
+                       segs_lds, s, ba);
     hipLaunchKernelGGL((part_sort_kernel<kSegThreads, 1>),
                        dim3((int)std::min<int64_t>(parts, 2 * 256)), dim3(kSegThreads), seg_lds,
-                       sb, ba);
+                       s, ba);
     hipLaunchKernelGGL(big_sort_kernel, dim3(bg), dim3(kThreads), big_lds, sb, ba);
     if (fe) {
         if ((e = hipGetLastError()) != hipSuccess)
