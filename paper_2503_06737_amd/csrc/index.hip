@@ -399,14 +399,19 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
 {
     const int t = blockIdx.x;
     const int R = 1 << a.msd_bits;
+    // the kMsdRadixMax threads form G groups of R, one thread per digit in
+    // each; group g takes tiles [g * ntiles / G, (g + 1) * ntiles / G)
+    const int G = kMsdRadixMax / R;
+    const int d = threadIdx.x & (R - 1), g = threadIdx.x / R;
+    const int tlo = (int)((int64_t)a.ntiles * g / G), thi = (int)((int64_t)a.ntiles * (g + 1) / G);
     __shared__ uint32_t wsum[kMsdRadixMax / kWave];
+    __shared__ uint32_t part[kMsdRadixMax];
     __shared__ uint32_t bres[2];
-    const int d = threadIdx.x;
     uint32_t *th = a.tile_hist + (int64_t)t * a.ntiles * R + d;
     uint32_t c = 0;
-    if (d < R) {
-        int tile = 0;
-        for (; tile + 8 <= a.ntiles; tile += 8) {
+    {
+        int tile = tlo;
+        for (; tile + 8 <= thi; tile += 8) {
             uint32_t v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
@@ -415,20 +420,34 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
             for (int u = 0; u < 8; ++u)
                 c += v[u];
         }
-        for (; tile < a.ntiles; ++tile)
+        for (; tile < thi; ++tile)
             c += th[(int64_t)tile * R];
-        a.ghist[(t << a.msd_bits) + d] = c;
     }
+    part[threadIdx.x] = c;
+    __syncthreads();
+    // the digit's total, and the count of its keys in the earlier groups' tiles
+    uint32_t total = 0, before = 0;
+    for (int q = 0; q < G; ++q) {
+        const uint32_t v = part[q * R + d];
+        total += v;
+        before += q < g ? v : 0u;
+    }
+    // group 0 (threads below R) holds the digits for the scans
+    const bool lead = g == 0;
+    c = lead ? total : 0u;
+    if (lead)
+        a.ghist[(t << a.msd_bits) + d] = c;
     uint32_t run = scan_excl(c, R, wsum);
-    const bool big = d < R && c > (uint32_t)kSegSmall &&
-                     !table_complete(a.tor, a.tand, t, a.msd_bits);
+    const bool big = lead && c > (uint32_t)kSegSmall && !table_complete(a.tor, a.tand, t, a.msd_bits);
     const uint32_t ntl = big ? (c + kTile - 1) / kTile : 0u;
     const uint32_t bi = scan_excl(big ? 1u : 0u, R, wsum);
     const uint32_t ti = scan_excl(ntl, R, wsum);
-    if (d == R - 1) {
+    if (threadIdx.x == R - 1) {
         bres[0] = atomicAdd(&a.bcount[0], bi + (big ? 1u : 0u));
         bres[1] = atomicAdd(&a.bcount[2], ti + ntl);
     }
+    if (lead)
+        part[d] = run; // the digit's segment start, for the other groups
     __syncthreads();
     if (big) {
         const uint32_t b0 = bres[0] + bi, t0 = bres[1] + ti;
@@ -444,11 +463,11 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
             a.btile[2 * (t0 + k) + 1] = k;
         }
     }
-    if (d >= R)
-        return;
-    a.seg_start[(t << a.msd_bits) + d] = run;
-    int tile = 0;
-    for (; tile + 8 <= a.ntiles; tile += 8) {
+    if (lead)
+        a.seg_start[(t << a.msd_bits) + d] = run;
+    run = part[d] + before;
+    int tile = tlo;
+    for (; tile + 8 <= thi; tile += 8) {
         uint32_t v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
@@ -459,7 +478,7 @@ __global__ __launch_bounds__(kMsdRadixMax) void msd_scan_kernel(BuildArgs a)
             run += v[u];
         }
     }
-    for (; tile < a.ntiles; ++tile) {
+    for (; tile < thi; ++tile) {
         const uint32_t v = th[(int64_t)tile * R];
         th[(int64_t)tile * R] = run;
         run += v;
