@@ -52,6 +52,9 @@ constexpr int kMsdTile = kThreads * kMsdItems;
 // Workgroups of a launch are dealt to the 8 XCDs (each with its own L2) in
 // turn: workgroup i runs on XCD i % 8.
 constexpr int kXcds = 8;
+// workgroups per table of the digit recount (tables whose top key bit does
+// not vary; for digests every workgroup exits at once)
+constexpr int kMsdUpGrid = 64;
 constexpr int kSegThreads = 512;
 constexpr int kSegSmall = kSegThreads * kItems; // 4096: segments sorted by kSegThreads
 // segments of at most 2048 keys take a 256-thread workgroup with half the
@@ -90,6 +93,8 @@ struct BuildArgs {
                           // big tiles, parts of 1..2048 keys, parts of 2049..4096 keys
     uint32_t *plist;      // [2][2 * L * 2^B][3]: those parts (table, start, size)
     uint32_t *stack;      // [grid][kStackMax][3]: start, size, buffer
+    uint64_t *hstat;      // [nhstat] run-head status words and counters, zeroed at the start
+    int64_t nhstat;
 };
 
 constexpr int kBig = 8;    // words per big-segment entry
@@ -187,6 +192,9 @@ __global__ __launch_bounds__(256) void build_init_kernel(BuildArgs a)
             a.tand[i] = ~0ull;
         }
     }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.nhstat;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a.hstat[i] = 0;
     // the counters do not depend on nseg (which can be as small as 2)
     if (blockIdx.x == 0 && threadIdx.x < kCounts)
         a.bcount[threadIdx.x] = 0;
@@ -365,28 +373,33 @@ __global__ __launch_bounds__(kThreads) void msd_up_kernel(BuildArgs a)
         return;
     const int R = 1 << a.msd_bits;
     __shared__ uint32_t h[kMsdRadixMax];
-    for (int i = threadIdx.x; i < R; i += blockDim.x)
-        h[i] = 0;
-    __syncthreads();
     const int shift = top_shift(a.tor[t] & ~a.tand[t], a.msd_bits);
     const uint64_t cmask = compact_mask(a.tor[t], a.tand[t], a.msd_bits);
     const uint64_t *k = a.kin + (int64_t)t * a.key_ld;
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    uint64_t v[kItems];
+    // workgroups take the table's tiles in turn (the grid is capped: for
+    // digest keys every workgroup exits at once)
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        for (int i = threadIdx.x; i < R; i += blockDim.x)
+            h[i] = 0;
+        __syncthreads();
+        const int64_t base = (int64_t)tile * kTile;
+        uint64_t v[kItems];
 #pragma unroll
-    for (int it = 0; it < kItems; ++it)
-        v[it] = k[min(base + it * kThreads + threadIdx.x, a.n - 1)];
+        for (int it = 0; it < kItems; ++it)
+            v[it] = k[min(base + it * kThreads + threadIdx.x, a.n - 1)];
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        const int64_t i = base + it * kThreads + threadIdx.x;
-        if (i < a.n)
-            hist_add(h, cmask ? compact_bits(v[it], cmask)
-                              : (uint32_t)(v[it] >> shift) & (uint32_t)(R - 1));
+        for (int it = 0; it < kItems; ++it) {
+            const int64_t i = base + it * kThreads + threadIdx.x;
+            if (i < a.n)
+                hist_add(h, cmask ? compact_bits(v[it], cmask)
+                                  : (uint32_t)(v[it] >> shift) & (uint32_t)(R - 1));
+        }
+        __syncthreads();
+        uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + tile) * R;
+        for (int i = threadIdx.x; i < R; i += blockDim.x)
+            th[i] = h[i];
+        __syncthreads();
     }
-    __syncthreads();
-    uint32_t *th = a.tile_hist + ((int64_t)t * a.ntiles + blockIdx.x) * R;
-    for (int i = threadIdx.x; i < R; i += blockDim.x)
-        th[i] = h[i];
 }
 
 // ghist[t][d] <- size of segment d (the sum of the tile counts);
@@ -1550,13 +1563,6 @@ struct HeadArgs {
 constexpr uint64_t kHeadAgg = 1ull << 62, kHeadPre = 2ull << 62;
 constexpr int kSpinMax = 1 << 16; // polls of one status word (about 0.1 s)
 
-__global__ __launch_bounds__(256) void fill_u64_kernel(uint64_t *p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
-}
-
 // A 64-bit value from the lane below (wave_shr:1 on each half); lane 0
 // receives `fill`.
 __device__ __forceinline__ uint64_t lane_below(uint64_t x, uint64_t fill)
@@ -1934,6 +1940,9 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     ba.bcount = (uint32_t *)(wb + wl.bcount);
     ba.plist = (uint32_t *)(wb + wl.plist);
     ba.stack = (uint32_t *)(wb + wl.stack);
+    // run-head status words, the tile counters and the error count after them
+    ba.hstat = (uint64_t *)(wb + wl.hstat);
+    ba.nhstat = (int64_t)L * wl.nhtiles + 8 * (int64_t)L + 1;
 
     const size_t scatter_lds = sizeof(ScatterLds<kMsdRadixMax, kMsdItems>);
     const size_t seg_lds = sizeof(SegLds<kSegThreads>);
@@ -1964,7 +1973,8 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     dim3 tiles(wl.ntiles, L);
     hipLaunchKernelGGL(build_init_kernel, dim3((nseg + 255) / 256), dim3(256), 0, s, ba);
     hipLaunchKernelGGL(mask_up_kernel, tiles, dim3(kThreads), 0, s, ba);
-    hipLaunchKernelGGL(msd_up_kernel, tiles, dim3(kThreads), 0, s, ba);
+    hipLaunchKernelGGL(msd_up_kernel, dim3(std::min(wl.ntiles, kMsdUpGrid), L), dim3(kThreads), 0, s,
+                       ba);
     hipLaunchKernelGGL(msd_scan_kernel, dim3(L), dim3(kMsdRadixMax), 0, s, ba);
     constexpr int tpm = kMsdTile / kTile;
     const int64_t npair = (int64_t)((wl.ntiles + tpm - 1) / tpm) * L;
@@ -2048,9 +2058,6 @@ extern "C" lsh_status lsh_build_index(const uint64_t *keys, int64_t key_ld, int6
     ha.ukeys = idx->ukeys;
     ha.offs = idx->offs;
     ha.nuniq = idx->nuniq;
-    const int64_t nstat = (int64_t)L * wl.nhtiles + 8 * (int64_t)L + 1;
-    const unsigned fill_grid = (unsigned)(nstat / 256 < 1024 ? nstat / 256 + 1 : 1024);
-    hipLaunchKernelGGL(fill_u64_kernel, dim3(fill_grid), dim3(256), 0, s, ha.status, nstat);
     hipLaunchKernelGGL(head_kernel, dim3(wl.nhtiles, L), dim3(kHeadThreads), 0, s, ha);
     e = hipGetLastError();
     if (e != hipSuccess)
