@@ -296,3 +296,26 @@ def test_builds_on_two_streams_and_threads_read_back_on_their_own_stream():
                 u = int(nu[t])
                 assert (uk[t, :u] == ref["ukeys"][t, :u]).all()
                 assert (of[t, :u + 1] == ref["offs"][t, :u + 1]).all()
+
+
+def test_side_stream_equal_to_the_main_stream():
+    """A side stream that is the main stream itself forks nothing: the build
+    runs on that stream alone and equals the oracle's (heavy buckets, so the
+    big-segment kernels run)."""
+    import torch
+    g = _rng(23)
+    n = 30000
+    keys = g.integers(0, 2**63, (3, n), dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    keys[g.random((3, n)) < 0.35] = np.uint64(0x9123456789ABCDEF)
+    ref = oracle.build_index(keys, 0)
+    idx = lsh.lsh_build_index(to_dev(keys), side_stream=torch.cuda.current_stream())
+    assert idx.check() == (0, 0)
+    sid, uk, of, nu = idx.arrays()
+    nu = to_host(nu)
+    assert nu.tolist() == ref["nuniq"].tolist()
+    assert (to_host(sid, np.uint32) == ref["sorted_ids"]).all()
+    uk, of = to_host(uk, np.uint64), to_host(of, np.uint32)
+    for t in range(3):
+        u = int(nu[t])
+        assert (uk[t, :u] == ref["ukeys"][t, :u]).all()
+        assert (of[t, :u + 1] == ref["offs"][t, :u + 1]).all()
