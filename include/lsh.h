@@ -345,11 +345,22 @@ lsh_status lsh_build_check_async(const void *workspace, size_t ws_bytes, int64_t
  *   metric: LSH_E2LSH = Euclidean distance, LSH_SRP = 1 - cos (cos = 0 when a
  *   norm is 0).  Output per query: ids[q*k + r] (int64, -1 pad), score[q*k + r]
  *   (FP32, +inf pad) in ascending (score, id) order; ncand[q] = number of
- *   distinct candidates (any output may be NULL except ids).  k: 1..64. */
+ *   distinct candidates (any output may be NULL except ids).  k: 1..64.
+ *   workspace: NULL, or lsh_query_workspace_bytes(nq, k) bytes (256-byte
+ *   aligned) that are all zero before the first call; every call leaves them
+ *   zero, and calls that overlap on one workspace race.  With it, a batch of
+ *   too few queries to fill the GPU scores each query with up to four
+ *   workgroups, which merge their top-k lists; the answers are the same.
+ *   ENOMEM if the workspace is smaller than that. */
 lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, const lsh_points *base,
                      const lsh_points *Q, const uint64_t *qkeys, int64_t qkey_ld, int32_t k,
                      int64_t id_watermark, int32_t metric, int64_t *ids, float *score,
-                     int32_t *ncand, void *stream);
+                     int32_t *ncand, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of the optional lsh_query workspace for nq queries with k results
+ * each: 0 when nq is 0 or above 256 (such batches fill the GPU without it)
+ * or k is outside 1..64. */
+size_t lsh_query_workspace_bytes(int64_t nq, int32_t k);
 
 /* ------------------------------------------------------------------ misc */
 

@@ -16,6 +16,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lsh_internal.h"
@@ -27,6 +28,10 @@ namespace lsh {
 constexpr int kQThreads = 256;
 constexpr int kQThreadsSolo = 512;
 constexpr int kMaxK = 64;
+// a query's candidates are scored by up to kQuerySplit workgroups when the
+// batch leaves CUs idle (batches of at most kSplitQueries queries)
+constexpr int kQuerySplit = 4;
+constexpr int kSplitQueries = 256;
 constexpr int kMaxSeg = 16;
 constexpr int kMaxLists = 1024;   // nseg * L
 
@@ -91,6 +96,12 @@ struct QueryArgs {
     int64_t *ids;
     float *score;
     int32_t *ncand;
+    // split > 1: workgroups per query; each keeps the top-k of its share of
+    // the candidates in part[q][split][k] and the last to finish (ticket[q])
+    // merges them and clears its ticket
+    int32_t split;
+    uint32_t *ticket;
+    uint64_t *part;
 };
 
 // OCP E4M3FN -> FP32 by the gfx950 conversion instruction: exact for every
@@ -656,7 +667,7 @@ query_kernel(QueryArgs a)
     __shared__ uint32_t s_ncand, s_hi, s_wcount, s_ucount;
     __shared__ uint32_t s_hist[kWinBins];
 
-    const int q = blockIdx.x;
+    const int q = blockIdx.x / a.split, share = blockIdx.x % a.split;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int nl = a.nseg * a.L;
 
@@ -797,10 +808,12 @@ query_kernel(QueryArgs a)
         __syncthreads();
         const uint32_t uc = s_ucount;
         // score: a wave takes NR candidates c, c + QW, ... together
-        // (their loads overlap); those past the end repeat c
+        // (their loads overlap); those past the end repeat c.  Blocks of
+        // NR * QW candidates go to the query's workgroups in turn.
         auto score_all = [&](auto nr_tag, auto scorer) {
             constexpr int NR = decltype(nr_tag)::value;
-            for (uint32_t c = wid; c < uc; c += NR * QW) {
+            for (uint32_t c = wid + (uint32_t)share * NR * QW; c < uc;
+                 c += (uint32_t)NR * QW * (uint32_t)a.split) {
                 int64_t row[NR];
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
@@ -827,6 +840,9 @@ query_kernel(QueryArgs a)
         constexpr int NRV = QShape<QT>::nr;
         using nrv = std::integral_constant<int, NRV>;
         using nr2 = std::integral_constant<int, 2>;
+        // the block of candidates that entry e belongs to is this workgroup's
+        const uint32_t nrb = (uint32_t)(a.vec4 ? NRV : 2) * QW;
+        auto mine = [&](uint32_t e) { return (e / nrb) % (uint32_t)a.split == (uint32_t)share; };
         if (a.vec4)
             score_all(nrv{}, [&](const int64_t (&row)[NRV], float (&acc)[NRV], float (&xx)[NRV]) {
                 score_rows_v4<NRV>(a, qv, row, acc, xx);
@@ -853,6 +869,8 @@ query_kernel(QueryArgs a)
         for (int e = tid; e < m2; e += QT) {
             if (e >= (int)uc)
                 sbuf[e] = e < tot ? topk[e - uc] : ~0ull;
+            else if (!mine((uint32_t)e))
+                sbuf[e] = ~0ull; // another workgroup's candidate
         }
         __syncthreads();
         sort_keys<QW, QShape<QT>::sort_cpw>(sbuf, m2);
@@ -865,7 +883,41 @@ query_kernel(QueryArgs a)
         __syncthreads();
     }
 
-    const int kc = s_kcur;
+    int kc = s_kcur;
+    if (a.split > 1) {
+        // publish this share's top-k (entries past it are ~0, which sort
+        // last); the last workgroup of the query to arrive merges all shares
+        uint64_t *mp = a.part + ((int64_t)q * a.split + share) * a.k;
+        for (int r = tid; r < a.k; r += QT)
+            mp[r] = r < kc ? topk[r] : ~0ull;
+        __threadfence();
+        __syncthreads();
+        __shared__ uint32_t s_last;
+        if (tid == 0)
+            s_last = atomicAdd(&a.ticket[q], 1u) == (uint32_t)a.split - 1;
+        __syncthreads();
+        if (!s_last)
+            return;
+        __threadfence();
+        const int tot = a.split * a.k;
+        int m2 = 1;
+        while (m2 < tot)
+            m2 <<= 1;
+        const uint64_t *qp = a.part + (int64_t)q * a.split * a.k;
+        for (int e = tid; e < m2; e += QT)
+            sbuf[e] = e < tot ? __hip_atomic_load(&qp[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : ~0ull;
+        __syncthreads();
+        sort_keys<QW, QShape<QT>::sort_cpw>(sbuf, m2);
+        for (int e = tid; e < a.k; e += QT)
+            topk[e] = sbuf[e];
+        if (tid == 0)
+            a.ticket[q] = 0u; // zero again for the next call
+        __syncthreads();
+        kc = 0;
+        for (int e = 0; e < a.k && sbuf[e] != ~0ull; ++e)
+            kc = e + 1;
+    }
     for (int r = tid; r < a.k; r += QT) {
         int64_t id = -1;
         float sc = INFINITY;
@@ -881,12 +933,31 @@ query_kernel(QueryArgs a)
         a.ncand[q] = (int32_t)s_ncand;
 }
 
+// Workspace of a split batch: tickets [kSplitQueries] at a fixed place (they
+// stay zero between calls, whatever nq a call has), then the shares' top-k
+// lists [nq][kQuerySplit][k], written before they are read.
+constexpr size_t kTicketBytes = (size_t)kSplitQueries * 4;
+static_assert(kTicketBytes % 256 == 0, "the lists start 256-byte aligned");
+
+size_t query_ws_bytes(int64_t nq, int32_t k)
+{
+    if (nq < 1 || nq > kSplitQueries || k < 1 || k > kMaxK)
+        return 0;
+    return kTicketBytes + (size_t)nq * kQuerySplit * (size_t)k * 8;
+}
+
 } // namespace lsh
+
+extern "C" size_t lsh_query_workspace_bytes(int64_t nq, int32_t k)
+{
+    return lsh::query_ws_bytes(nq, k);
+}
 
 extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, const lsh_points *base,
                                 const lsh_points *Q, const uint64_t *qkeys, int64_t qkey_ld,
                                 int32_t k, int64_t id_watermark, int32_t metric, int64_t *ids,
-                                float *score, int32_t *ncand, void *stream)
+                                float *score, int32_t *ncand, void *workspace, size_t ws_bytes,
+                                void *stream)
 {
     using namespace lsh;
     if (!segs || nseg < 1 || nseg > kMaxSeg)
@@ -962,7 +1033,24 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
     a.ids = ids;
     a.score = score;
     a.ncand = ncand;
-    const bool solo = Q->n <= device_cu_count();
+    // a batch that leaves CUs idle scores each query with several workgroups
+    // when a workspace is given
+    const int cus = device_cu_count();
+    a.split = 1;
+    if (workspace && Q->n <= kSplitQueries) {
+        const size_t need = query_ws_bytes(Q->n, k);
+        if (ws_bytes < need || ((uintptr_t)workspace & 255))
+            LSH_FAIL(LSH_ENOMEM, "query workspace needs %zu bytes (256-aligned), got %zu", need,
+                     ws_bytes);
+        // the shares publish their lists behind a device-scope fence, which
+        // costs more than the split saves once the split grid passes a
+        // quarter of the CUs
+        a.split = (int32_t)std::min<int64_t>(kQuerySplit, std::max<int64_t>(1, cus / (4 * Q->n)));
+        a.ticket = (uint32_t *)workspace;
+        a.part = (uint64_t *)((unsigned char *)workspace + kTicketBytes);
+    }
+    const int64_t nwg = Q->n * a.split;
+    const bool solo = nwg <= cus;
     const int nl = nseg * a.L;
     const size_t lds = solo ? query_lds_bytes<kQThreadsSolo>(Q->d, nl)
                             : query_lds_bytes<kQThreads>(Q->d, nl);
@@ -970,10 +1058,10 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
                           : (const void *)query_kernel<kQThreads>;
     LSH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     if (solo)
-        hipLaunchKernelGGL(query_kernel<kQThreadsSolo>, dim3((unsigned)Q->n), dim3(kQThreadsSolo),
+        hipLaunchKernelGGL(query_kernel<kQThreadsSolo>, dim3((unsigned)nwg), dim3(kQThreadsSolo),
                            lds, (hipStream_t)stream, a);
     else
-        hipLaunchKernelGGL(query_kernel<kQThreads>, dim3((unsigned)Q->n), dim3(kQThreads), lds,
+        hipLaunchKernelGGL(query_kernel<kQThreads>, dim3((unsigned)nwg), dim3(kQThreads), lds,
                            (hipStream_t)stream, a);
     LSH_LAUNCHED("query_kernel");
     return LSH_OK;

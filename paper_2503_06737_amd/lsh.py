@@ -24,7 +24,8 @@ STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ENOMEM", -3: "LSH_EHIP", -5: "
 
 EXPORTS = ("lsh_hash_dense_bf16", "lsh_hash_cs_tables", "lsh_hash_hcs_tables", "lsh_quantize_rows", "lsh_build_check_async", "lsh_hash_workspace_bytes", "lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_dense",
            "lsh_index_bytes", "lsh_build_workspace_bytes", "lsh_build_index",
-           "lsh_index_get_view", "lsh_index_free", "lsh_query", "lsh_last_error", "lsh_version")
+           "lsh_index_get_view", "lsh_index_free", "lsh_query", "lsh_query_workspace_bytes",
+           "lsh_last_error", "lsh_version")
 
 
 class LshError(RuntimeError):
@@ -87,7 +88,9 @@ def lib() -> C.CDLL:
         L.lsh_build_check.argtypes = [vp, sz, i64, i32, vp, vp]
         L.lsh_build_check_async.argtypes = [vp, sz, i64, i32, vp, vp]
         L.lsh_quantize_rows.argtypes = [vp, i64, i32, i64, i32, vp, i64, vp, vp]
-        L.lsh_query.argtypes = [vp, i32, vp, vp, vp, i64, i32, i64, i32, vp, vp, vp, vp]
+        L.lsh_query.argtypes = [vp, i32, vp, vp, vp, i64, i32, i64, i32, vp, vp, vp, vp, sz, vp]
+        L.lsh_query_workspace_bytes.argtypes = [i64, i32]
+        L.lsh_query_workspace_bytes.restype = sz
         L.lsh_last_error.restype = C.c_char_p
         L.lsh_version.restype = i32
         for fn in ("lsh_hash_cs", "lsh_hash_cs_noalloc", "lsh_hash_hcs", "lsh_hash_cs_tables",
@@ -341,9 +344,25 @@ def lsh_build_index(keys: torch.Tensor, id_base: int = 0, mem: torch.Tensor | No
     return Index(h, mem, n, L, id_base, ws)
 
 
+# Query workspaces, one per (device, stream): zero when made, and every call
+# leaves them zero; calls on one stream run one after another.
+_QUERY_WS: dict = {}
+
+
+def _query_ws(dev, stream_ptr: int) -> torch.Tensor:
+    key = (str(dev), stream_ptr)
+    ws = _QUERY_WS.get(key)
+    if ws is None:
+        ws = _QUERY_WS[key] = torch.zeros(lib().lsh_query_workspace_bytes(256, 64),
+                                          dtype=torch.uint8, device=dev)
+    return ws
+
+
 def lsh_query(segs, base, Q, qkeys, *, k, watermark=None, metric=E2LSH, base_scale=None,
-              q_scale=None, ncand=True):
-    """Top-k of every query row; returns (ids [nq][k] int64, score [nq][k] f32, ncand [nq])."""
+              q_scale=None, ncand=True, split=True):
+    """Top-k of every query row; returns (ids [nq][k] int64, score [nq][k] f32, ncand [nq]).
+    split: let a small batch score each query with several workgroups (through
+    a workspace kept per device and stream); the answers are the same."""
     segs = list(segs)
     nq = Q.shape[0]
     ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
@@ -352,7 +371,9 @@ def lsh_query(segs, base, Q, qkeys, *, k, watermark=None, metric=E2LSH, base_sca
     arr = (C.c_void_p * len(segs))(*[s.handle.value for s in segs])
     pb, pq = points(base, base_scale), points(Q, q_scale)
     wm = (1 << 62) if watermark is None else int(watermark)
+    st = _stream()
+    ws = _query_ws(Q.device, st.value or 0) if split and 0 < nq <= 256 else None
     _check(lib().lsh_query(arr, len(segs), C.byref(pb), C.byref(pq), _ptr(qkeys),
                            qkeys.stride(0) if nq else 0, k, wm, metric, _ptr(ids), _ptr(score),
-                           _ptr(nc), _stream()))
+                           _ptr(nc), _ptr(ws), 0 if ws is None else ws.numel(), st))
     return ids, score, nc

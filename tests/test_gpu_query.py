@@ -135,3 +135,32 @@ def test_query_low_precision_base(kind):
     assert (to_host(keys, np.uint64) == rk).all() and (to_host(qkeys, np.uint64) == rqk).all()
     ref = oracle.query([oracle.build_index(rk)], x64, Q.astype(np.float64), rqk, 10, 3000, 1)
     _compare(ids, scv, nc, *ref, what=f"{kind} base")
+
+
+def test_split_batches_of_changing_size_equal_unsplit():
+    """Small batches score each query with several workgroups, which merge
+    their top-k through the workspace (tickets that every call leaves zero,
+    then the lists).  Batches of 2, 100, 3, 256, 1 and 40 queries in turn on
+    one stream and workspace, with k from 1 to 64, give exactly the unsplit
+    kernel's answers; the unsplit ones match the oracle (checked above)."""
+    g = np.random.default_rng(31)
+    n, d, K, L, m = 6000, 256, 8, 16, 128
+    mu = g.standard_normal((20, d))
+    x = (mu[g.integers(0, 20, n)] + 0.1 * g.standard_normal((n, d))).astype(np.float32)
+    Q = (mu[g.integers(0, 20, 400)] + 0.1 * g.standard_normal((400, d))).astype(np.float32)
+    h, s = synth.cs_state(d, m, 5)
+    b = synth.shifts(m, 16.0, 5)
+    kw = dict(family=oracle.E2LSH, K=K, L=L, w=16.0, b=to_dev(b))
+    xd, Qd = to_dev(x), to_dev(Q)
+    keys = lsh.lsh_hash_cs(xd, to_dev(h), to_dev(s), **kw)["keys"]
+    qkeys = lsh.lsh_hash_cs(Qd, to_dev(h), to_dev(s), **kw)["keys"]
+    idx = lsh.lsh_build_index(keys)
+    lo = 0
+    for nq, k in ((2, 10), (100, 64), (3, 1), (256, 10), (1, 64), (40, 7)):
+        Qs, qks = Qd[lo:lo + nq].contiguous(), qkeys[:, lo:lo + nq].contiguous()
+        lo = (lo + nq) % 100
+        a = lsh.lsh_query([idx], xd, Qs, qks, k=k, metric=oracle.E2LSH, split=False)
+        bsp = lsh.lsh_query([idx], xd, Qs, qks, k=k, metric=oracle.E2LSH, split=True)
+        for u, v in zip(a, bsp):
+            assert np.array_equal(to_host(u), to_host(v)), (nq, k)
+        assert (to_host(a[2]) > 0).any()
