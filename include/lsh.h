@@ -347,10 +347,10 @@ lsh_status lsh_build_check_async(const void *workspace, size_t ws_bytes, int64_t
  *   (FP32, +inf pad) in ascending (score, id) order; ncand[q] = number of
  *   distinct candidates (any output may be NULL except ids).  k: 1..64.
  *   workspace: NULL, or lsh_query_workspace_bytes(nq, k) bytes (256-byte
- *   aligned) that are all zero before the first call; every call leaves them
- *   zero, and calls that overlap on one workspace race.  With it, a batch of
- *   too few queries to fill the GPU scores each query with up to four
- *   workgroups, which merge their top-k lists; the answers are the same.
+ *   aligned, any contents; calls that overlap on one workspace race).  With
+ *   it, a batch of too few queries to fill the GPU scores each query with up
+ *   to four workgroups, each leaving the top-k of its share of the candidates
+ *   there for a second kernel that merges them; the answers are the same.
  *   ENOMEM if the workspace is smaller than that. */
 lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, const lsh_points *base,
                      const lsh_points *Q, const uint64_t *qkeys, int64_t qkey_ld, int32_t k,

@@ -96,11 +96,9 @@ struct QueryArgs {
     int64_t *ids;
     float *score;
     int32_t *ncand;
-    // split > 1: workgroups per query; each keeps the top-k of its share of
-    // the candidates in part[q][split][k] and the last to finish (ticket[q])
-    // merges them and clears its ticket
+    // split > 1: workgroups per query; each leaves the top-k of its share of
+    // the candidates in part[q][split][k] for query_merge_kernel
     int32_t split;
-    uint32_t *ticket;
     uint64_t *part;
 };
 
@@ -883,40 +881,16 @@ query_kernel(QueryArgs a)
         __syncthreads();
     }
 
-    int kc = s_kcur;
+    const int kc = s_kcur;
     if (a.split > 1) {
-        // publish this share's top-k (entries past it are ~0, which sort
-        // last); the last workgroup of the query to arrive merges all shares
+        // this share's top-k (entries past it are ~0, which sort last) for
+        // the merge kernel; every share counted the same candidates
         uint64_t *mp = a.part + ((int64_t)q * a.split + share) * a.k;
         for (int r = tid; r < a.k; r += QT)
             mp[r] = r < kc ? topk[r] : ~0ull;
-        __threadfence();
-        __syncthreads();
-        __shared__ uint32_t s_last;
-        if (tid == 0)
-            s_last = atomicAdd(&a.ticket[q], 1u) == (uint32_t)a.split - 1;
-        __syncthreads();
-        if (!s_last)
-            return;
-        __threadfence();
-        const int tot = a.split * a.k;
-        int m2 = 1;
-        while (m2 < tot)
-            m2 <<= 1;
-        const uint64_t *qp = a.part + (int64_t)q * a.split * a.k;
-        for (int e = tid; e < m2; e += QT)
-            sbuf[e] = e < tot ? __hip_atomic_load(&qp[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                              : ~0ull;
-        __syncthreads();
-        sort_keys<QW, QShape<QT>::sort_cpw>(sbuf, m2);
-        for (int e = tid; e < a.k; e += QT)
-            topk[e] = sbuf[e];
-        if (tid == 0)
-            a.ticket[q] = 0u; // zero again for the next call
-        __syncthreads();
-        kc = 0;
-        for (int e = 0; e < a.k && sbuf[e] != ~0ull; ++e)
-            kc = e + 1;
+        if (tid == 0 && share == 0 && a.ncand)
+            a.ncand[q] = (int32_t)s_ncand;
+        return;
     }
     for (int r = tid; r < a.k; r += QT) {
         int64_t id = -1;
@@ -933,17 +907,37 @@ query_kernel(QueryArgs a)
         a.ncand[q] = (int32_t)s_ncand;
 }
 
-// Workspace of a split batch: tickets [kSplitQueries] at a fixed place (they
-// stay zero between calls, whatever nq a call has), then the shares' top-k
-// lists [nq][kQuerySplit][k], written before they are read.
-constexpr size_t kTicketBytes = (size_t)kSplitQueries * 4;
-static_assert(kTicketBytes % 256 == 0, "the lists start 256-byte aligned");
+// The k best of a query's split * k share entries (distinct, except the ~0
+// padding): entry i goes to rank #{j : e_j < e_i, or e_j == e_i and j < i}.
+// One workgroup per query, one thread per entry (split * k <= 256).
+__global__ __launch_bounds__(256) void query_merge_kernel(const uint64_t *part, int split, int k,
+                                                          int64_t *ids, float *score)
+{
+    __shared__ uint64_t e[kQuerySplit * kMaxK];
+    const int q = blockIdx.x, n = split * k, i = threadIdx.x;
+    if (i < n)
+        e[i] = part[(int64_t)q * n + i];
+    __syncthreads();
+    if (i >= n)
+        return;
+    const uint64_t v = e[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j)
+        rank += (e[j] < v || (e[j] == v && j < i)) ? 1 : 0;
+    if (rank < k) {
+        const bool pad = v == ~0ull;
+        ids[(int64_t)q * k + rank] = pad ? -1 : (int64_t)(uint32_t)v;
+        if (score)
+            score[(int64_t)q * k + rank] = pad ? INFINITY : __uint_as_float((uint32_t)(v >> 32));
+    }
+}
 
+// Workspace of a split batch: the shares' top-k lists [nq][kQuerySplit][k].
 size_t query_ws_bytes(int64_t nq, int32_t k)
 {
     if (nq < 1 || nq > kSplitQueries || k < 1 || k > kMaxK)
         return 0;
-    return kTicketBytes + (size_t)nq * kQuerySplit * (size_t)k * 8;
+    return (size_t)nq * kQuerySplit * (size_t)k * 8;
 }
 
 } // namespace lsh
@@ -1042,12 +1036,8 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
         if (ws_bytes < need || ((uintptr_t)workspace & 255))
             LSH_FAIL(LSH_ENOMEM, "query workspace needs %zu bytes (256-aligned), got %zu", need,
                      ws_bytes);
-        // the shares publish their lists behind a device-scope fence, which
-        // costs more than the split saves once the split grid passes a
-        // quarter of the CUs
-        a.split = (int32_t)std::min<int64_t>(kQuerySplit, std::max<int64_t>(1, cus / (4 * Q->n)));
-        a.ticket = (uint32_t *)workspace;
-        a.part = (uint64_t *)((unsigned char *)workspace + kTicketBytes);
+        a.split = (int32_t)std::min<int64_t>(kQuerySplit, std::max<int64_t>(1, cus / Q->n));
+        a.part = (uint64_t *)workspace;
     }
     const int64_t nwg = Q->n * a.split;
     const bool solo = nwg <= cus;
@@ -1064,5 +1054,10 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
         hipLaunchKernelGGL(query_kernel<kQThreads>, dim3((unsigned)nwg), dim3(kQThreads), lds,
                            (hipStream_t)stream, a);
     LSH_LAUNCHED("query_kernel");
+    if (a.split > 1) {
+        hipLaunchKernelGGL(query_merge_kernel, dim3((unsigned)Q->n), dim3(256), 0,
+                           (hipStream_t)stream, (const uint64_t *)a.part, a.split, k, ids, score);
+        LSH_LAUNCHED("query_merge_kernel");
+    }
     return LSH_OK;
 }

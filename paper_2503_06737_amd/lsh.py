@@ -344,8 +344,8 @@ def lsh_build_index(keys: torch.Tensor, id_base: int = 0, mem: torch.Tensor | No
     return Index(h, mem, n, L, id_base, ws)
 
 
-# Query workspaces, one per (device, stream): zero when made, and every call
-# leaves them zero; calls on one stream run one after another.
+# Query workspaces, one per (device, stream): calls on one stream run one
+# after another, so they never overlap on theirs.
 _QUERY_WS: dict = {}
 
 

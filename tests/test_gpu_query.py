@@ -138,11 +138,11 @@ def test_query_low_precision_base(kind):
 
 
 def test_split_batches_of_changing_size_equal_unsplit():
-    """Small batches score each query with several workgroups, which merge
-    their top-k through the workspace (tickets that every call leaves zero,
-    then the lists).  Batches of 2, 100, 3, 256, 1 and 40 queries in turn on
-    one stream and workspace, with k from 1 to 64, give exactly the unsplit
-    kernel's answers; the unsplit ones match the oracle (checked above)."""
+    """Small batches score each query with several workgroups, whose top-k
+    lists a second kernel merges through the workspace.  Batches of 2, 100, 3,
+    256, 1 and 40 queries in turn on one stream and workspace, with k from 1
+    to 64, give exactly the unsplit kernel's answers; the unsplit ones match
+    the oracle (checked above)."""
     g = np.random.default_rng(31)
     n, d, K, L, m = 6000, 256, 8, 16, 128
     mu = g.standard_normal((20, d))
