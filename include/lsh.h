@@ -348,9 +348,10 @@ lsh_status lsh_build_check_async(const void *workspace, size_t ws_bytes, int64_t
  *   distinct candidates (any output may be NULL except ids).  k: 1..64.
  *   workspace: NULL, or lsh_query_workspace_bytes(nq, k) bytes (256-byte
  *   aligned, any contents; calls that overlap on one workspace race).  With
- *   it, a batch of too few queries to fill the GPU scores each query with up
- *   to four workgroups, each leaving the top-k of its share of the candidates
- *   there for a second kernel that merges them; the answers are the same.
+ *   it, a batch of at most 1024 queries scores each query with several
+ *   workgroups (up to four while they fit one per CU, else two), each
+ *   leaving the top-k of its share of the candidates there for a second
+ *   kernel that merges them; the answers are the same.
  *   ENOMEM if the workspace is smaller than that. */
 lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, const lsh_points *base,
                      const lsh_points *Q, const uint64_t *qkeys, int64_t qkey_ld, int32_t k,
@@ -358,8 +359,8 @@ lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, const lsh_point
                      int32_t *ncand, void *workspace, size_t ws_bytes, void *stream);
 
 /* Bytes of the optional lsh_query workspace for nq queries with k results
- * each: 0 when nq is 0 or above 256 (such batches fill the GPU without it)
- * or k is outside 1..64. */
+ * each: 0 when nq is 0 or above 1024 (such batches run unsplit) or k is
+ * outside 1..64. */
 size_t lsh_query_workspace_bytes(int64_t nq, int32_t k);
 
 /* ------------------------------------------------------------------ misc */

@@ -28,10 +28,10 @@ namespace lsh {
 constexpr int kQThreads = 256;
 constexpr int kQThreadsSolo = 512;
 constexpr int kMaxK = 64;
-// a query's candidates are scored by up to kQuerySplit workgroups when the
-// batch leaves CUs idle (batches of at most kSplitQueries queries)
+// a query's candidates are scored by up to kQuerySplit workgroups in batches
+// of at most kSplitQueries queries (see lsh_query)
 constexpr int kQuerySplit = 4;
-constexpr int kSplitQueries = 256;
+constexpr int kSplitQueries = 1024;
 constexpr int kMaxSeg = 16;
 constexpr int kMaxLists = 1024;   // nseg * L
 
@@ -1036,7 +1036,10 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
         if (ws_bytes < need || ((uintptr_t)workspace & 255))
             LSH_FAIL(LSH_ENOMEM, "query workspace needs %zu bytes (256-aligned), got %zu", need,
                      ws_bytes);
-        a.split = (int32_t)std::min<int64_t>(kQuerySplit, std::max<int64_t>(1, cus / Q->n));
+        // up to four ways while the split grid keeps one workgroup per CU (the
+        // 8-wave shape); batches of more queries than CUs run the 4-wave shape
+        // either way and gain from halving their heaviest queries' scoring
+        a.split = Q->n <= cus ? (int32_t)std::min<int64_t>(kQuerySplit, cus / Q->n) : 2;
         a.part = (uint64_t *)workspace;
     }
     const int64_t nwg = Q->n * a.split;

@@ -353,7 +353,7 @@ def _query_ws(dev, stream_ptr: int) -> torch.Tensor:
     key = (str(dev), stream_ptr)
     ws = _QUERY_WS.get(key)
     if ws is None:
-        ws = _QUERY_WS[key] = torch.zeros(lib().lsh_query_workspace_bytes(256, 64),
+        ws = _QUERY_WS[key] = torch.zeros(lib().lsh_query_workspace_bytes(1024, 64),
                                           dtype=torch.uint8, device=dev)
     return ws
 
@@ -372,7 +372,7 @@ def lsh_query(segs, base, Q, qkeys, *, k, watermark=None, metric=E2LSH, base_sca
     pb, pq = points(base, base_scale), points(Q, q_scale)
     wm = (1 << 62) if watermark is None else int(watermark)
     st = _stream()
-    ws = _query_ws(Q.device, st.value or 0) if split and 0 < nq <= 256 else None
+    ws = _query_ws(Q.device, st.value or 0) if split and 0 < nq <= 1024 else None
     _check(lib().lsh_query(arr, len(segs), C.byref(pb), C.byref(pq), _ptr(qkeys),
                            qkeys.stride(0) if nq else 0, k, wm, metric, _ptr(ids), _ptr(score),
                            _ptr(nc), _ptr(ws), 0 if ws is None else ws.numel(), st))

@@ -139,10 +139,10 @@ def test_query_low_precision_base(kind):
 
 def test_split_batches_of_changing_size_equal_unsplit():
     """Small batches score each query with several workgroups, whose top-k
-    lists a second kernel merges through the workspace.  Batches of 2, 100, 3,
-    256, 1 and 40 queries in turn on one stream and workspace, with k from 1
-    to 64, give exactly the unsplit kernel's answers; the unsplit ones match
-    the oracle (checked above)."""
+    lists a second kernel merges through the workspace.  Batches of 1 to 400
+    queries in turn on one stream and workspace, with k from 1 to 64, give
+    exactly the unsplit kernel's answers; the unsplit ones match the oracle
+    (checked above)."""
     g = np.random.default_rng(31)
     n, d, K, L, m = 6000, 256, 8, 16, 128
     mu = g.standard_normal((20, d))
@@ -156,9 +156,9 @@ def test_split_batches_of_changing_size_equal_unsplit():
     qkeys = lsh.lsh_hash_cs(Qd, to_dev(h), to_dev(s), **kw)["keys"]
     idx = lsh.lsh_build_index(keys)
     lo = 0
-    for nq, k in ((2, 10), (100, 64), (3, 1), (256, 10), (1, 64), (40, 7)):
+    for nq, k in ((2, 10), (100, 64), (3, 1), (256, 10), (1, 64), (40, 7), (400, 10), (300, 64)):
         Qs, qks = Qd[lo:lo + nq].contiguous(), qkeys[:, lo:lo + nq].contiguous()
-        lo = (lo + nq) % 100
+        lo = 0 if nq > 100 else (lo + nq) % 100
         a = lsh.lsh_query([idx], xd, Qs, qks, k=k, metric=oracle.E2LSH, split=False)
         bsp = lsh.lsh_query([idx], xd, Qs, qks, k=k, metric=oracle.E2LSH, split=True)
         for u, v in zip(a, bsp):
