@@ -858,23 +858,40 @@ query_kernel(QueryArgs a)
                 score_rows<LSH_FP8_E4M3FN, 2>(a, qv, row, acc, xx);
             });
         __syncthreads();
-        // merge with the running top-k
+        // merge with the running top-k.  A split query's workgroup sorts only
+        // its own scored entries: they are copied, its j-th block of nrb to
+        // j * nrb, into the upper part of the sort buffer (entries below kCap
+        // are read, entries from kCap on written), so its sort covers its
+        // share, not the whole window.
+        // (a share of at most kCap entries holds at most kCap / 2 + 2 blocks
+        // of at most NR * QW)
+        static_assert(pow2_at_least(kCap / 2 + 2 * QShape<QT>::nr * QW + kMaxK) <= kSortCap - kCap,
+                      "room for a share and the top-k above the window");
         const int kc = s_kcur;
-        int tot = (int)uc + kc;
+        uint64_t *mb = sbuf;
+        uint32_t nmine = uc;
+        if (a.split > 1) {
+            const uint32_t sp = (uint32_t)a.split;
+            mb = sbuf + kCap;
+            nmine = 0;
+            for (uint32_t bk = (uint32_t)share; bk * nrb < uc; bk += sp)
+                nmine += min(nrb, uc - bk * nrb);
+            for (uint32_t e = tid; e < uc; e += QT)
+                if (mine(e))
+                    mb[(e / nrb / sp) * nrb + e % nrb] = sbuf[e];
+        }
+        int tot = (int)nmine + kc;
         int m2 = 1;
         while (m2 < tot)
             m2 <<= 1;
-        for (int e = tid; e < m2; e += QT) {
-            if (e >= (int)uc)
-                sbuf[e] = e < tot ? topk[e - uc] : ~0ull;
-            else if (!mine((uint32_t)e))
-                sbuf[e] = ~0ull; // another workgroup's candidate
-        }
+        for (int e = tid; e < m2; e += QT)
+            if (e >= (int)nmine)
+                mb[e] = e < tot ? topk[e - nmine] : ~0ull;
         __syncthreads();
-        sort_keys<QW, QShape<QT>::sort_cpw>(sbuf, m2);
+        sort_keys<QW, QShape<QT>::sort_cpw>(mb, m2);
         int nk = tot < a.k ? tot : a.k;
         for (int e = tid; e < nk; e += QT)
-            topk[e] = sbuf[e];
+            topk[e] = mb[e];
         __syncthreads();
         if (tid == 0)
             s_kcur = nk;
