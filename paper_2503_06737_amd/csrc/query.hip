@@ -100,6 +100,7 @@ struct QueryArgs {
     // the candidates in part[q][split][k] for query_merge_kernel
     int32_t split;
     uint64_t *part;
+    uint32_t *pcount; // [q][split] distinct candidates of each share
 };
 
 // OCP E4M3FN -> FP32 by the gfx950 conversion instruction: exact for every
@@ -760,28 +761,59 @@ query_kernel(QueryArgs a)
         }
         __syncthreads();
         const uint32_t wc = s_wcount;
-        int p2 = 1;
-        while (p2 < (int)wc)
-            p2 <<= 1;
-        // gather the window's ids
-        for (uint32_t e = tid; e < (uint32_t)p2; e += QT) {
-            uint64_t v = ~0ull;
-            if (e < wc) {
-                int lo = 0, hi = nl; // list holding entry e: last li with pre[li] <= e
-                while (hi - lo > 1) {
-                    int mid = (lo + hi) >> 1;
-                    if (lst_pre[mid] <= e)
-                        lo = mid;
-                    else
-                        hi = mid;
-                }
-                while (lst_take[lo] == 0 || lst_pre[lo] + lst_take[lo] <= e)
-                    ++lo;
-                int sg = lo / a.L, t = lo % a.L;
-                v = a.seg[sg].ids[(int64_t)t * a.seg[sg].n + lst_cur[lo] + (e - lst_pre[lo])];
+        // id of window entry e (e < wc): the list holding it is the last li
+        // with pre[li] <= e
+        auto entry_id = [&](uint32_t e) {
+            int lo = 0, hi = nl;
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (lst_pre[mid] <= e)
+                    lo = mid;
+                else
+                    hi = mid;
             }
-            sbuf[e] = v;
+            while (lst_take[lo] == 0 || lst_pre[lo] + lst_take[lo] <= e)
+                ++lo;
+            int sg = lo / a.L, t = lo % a.L;
+            return a.seg[sg].ids[(int64_t)t * a.seg[sg].n + lst_cur[lo] + (e - lst_pre[lo])];
+        };
+        // the window's ids; a split query's workgroup keeps the ids that are
+        // its own (id % split == share), compacted in order
+        uint32_t wm = wc;
+        if (a.split > 1) {
+            constexpr int kPer = (kCap + QT - 1) / QT; // wc <= kCap
+            const uint32_t per = (wc + QT - 1) / QT;
+            const uint32_t e0 = (uint32_t)tid * per;
+            uint32_t idv[kPer];
+            uint32_t nk = 0;
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const uint32_t e = e0 + (uint32_t)i;
+                idv[i] = ~0u;
+                if ((uint32_t)i < per && e < wc) {
+                    const uint32_t id = entry_id(e);
+                    if (id % (uint32_t)a.split == (uint32_t)share) {
+                        idv[i] = id;
+                        ++nk;
+                    }
+                }
+            }
+            uint32_t tot;
+            uint32_t pos = block_excl_scan<QW>(nk, red, &tot);
+#pragma unroll
+            for (int i = 0; i < kPer; ++i)
+                if (idv[i] != ~0u)
+                    sbuf[pos++] = idv[i];
+            wm = tot;
+        } else {
+            for (uint32_t e = tid; e < wc; e += QT)
+                sbuf[e] = entry_id(e);
         }
+        int p2 = 1;
+        while (p2 < (int)wm)
+            p2 <<= 1;
+        for (uint32_t e = wm + tid; e < (uint32_t)p2; e += QT)
+            sbuf[e] = ~0ull;
         __syncthreads();
         for (int li = tid; li < nl; li += QT)
             lst_cur[li] += lst_take[li];
@@ -789,7 +821,7 @@ query_kernel(QueryArgs a)
         {
             // distinct ids, compacted in order: thread owns a contiguous run
             const int per = (p2 + QT - 1) / QT;
-            const int e0 = tid * per, e1 = e0 + per < (int)wc ? e0 + per : (int)wc;
+            const int e0 = tid * per, e1 = e0 + per < (int)wm ? e0 + per : (int)wm;
             uint32_t mine = 0;
             for (int e = e0; e < e1; ++e)
                 mine += (e == 0 || sbuf[e] != sbuf[e - 1]);
@@ -806,12 +838,10 @@ query_kernel(QueryArgs a)
         __syncthreads();
         const uint32_t uc = s_ucount;
         // score: a wave takes NR candidates c, c + QW, ... together
-        // (their loads overlap); those past the end repeat c.  Blocks of
-        // NR * QW candidates go to the query's workgroups in turn.
+        // (their loads overlap); those past the end repeat c
         auto score_all = [&](auto nr_tag, auto scorer) {
             constexpr int NR = decltype(nr_tag)::value;
-            for (uint32_t c = wid + (uint32_t)share * NR * QW; c < uc;
-                 c += (uint32_t)NR * QW * (uint32_t)a.split) {
+            for (uint32_t c = wid; c < uc; c += NR * QW) {
                 int64_t row[NR];
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
@@ -838,9 +868,6 @@ query_kernel(QueryArgs a)
         constexpr int NRV = QShape<QT>::nr;
         using nrv = std::integral_constant<int, NRV>;
         using nr2 = std::integral_constant<int, 2>;
-        // the block of candidates that entry e belongs to is this workgroup's
-        const uint32_t nrb = (uint32_t)(a.vec4 ? NRV : 2) * QW;
-        auto mine = [&](uint32_t e) { return (e / nrb) % (uint32_t)a.split == (uint32_t)share; };
         if (a.vec4)
             score_all(nrv{}, [&](const int64_t (&row)[NRV], float (&acc)[NRV], float (&xx)[NRV]) {
                 score_rows_v4<NRV>(a, qv, row, acc, xx);
@@ -858,40 +885,21 @@ query_kernel(QueryArgs a)
                 score_rows<LSH_FP8_E4M3FN, 2>(a, qv, row, acc, xx);
             });
         __syncthreads();
-        // merge with the running top-k.  A split query's workgroup sorts only
-        // its own scored entries: they are copied, its j-th block of nrb to
-        // j * nrb, into the upper part of the sort buffer (entries below kCap
-        // are read, entries from kCap on written), so its sort covers its
-        // share, not the whole window.
-        // (a share of at most kCap entries holds at most kCap / 2 + 2 blocks
-        // of at most NR * QW)
-        static_assert(pow2_at_least(kCap / 2 + 2 * QShape<QT>::nr * QW + kMaxK) <= kSortCap - kCap,
-                      "room for a share and the top-k above the window");
+        // merge with the running top-k
         const int kc = s_kcur;
-        uint64_t *mb = sbuf;
-        uint32_t nmine = uc;
-        if (a.split > 1) {
-            const uint32_t sp = (uint32_t)a.split;
-            mb = sbuf + kCap;
-            nmine = 0;
-            for (uint32_t bk = (uint32_t)share; bk * nrb < uc; bk += sp)
-                nmine += min(nrb, uc - bk * nrb);
-            for (uint32_t e = tid; e < uc; e += QT)
-                if (mine(e))
-                    mb[(e / nrb / sp) * nrb + e % nrb] = sbuf[e];
-        }
-        int tot = (int)nmine + kc;
+        int tot = (int)uc + kc;
         int m2 = 1;
         while (m2 < tot)
             m2 <<= 1;
-        for (int e = tid; e < m2; e += QT)
-            if (e >= (int)nmine)
-                mb[e] = e < tot ? topk[e - nmine] : ~0ull;
+        for (int e = tid; e < m2; e += QT) {
+            if (e >= (int)uc)
+                sbuf[e] = e < tot ? topk[e - uc] : ~0ull;
+        }
         __syncthreads();
-        sort_keys<QW, QShape<QT>::sort_cpw>(mb, m2);
+        sort_keys<QW, QShape<QT>::sort_cpw>(sbuf, m2);
         int nk = tot < a.k ? tot : a.k;
         for (int e = tid; e < nk; e += QT)
-            topk[e] = mb[e];
+            topk[e] = sbuf[e];
         __syncthreads();
         if (tid == 0)
             s_kcur = nk;
@@ -900,13 +908,13 @@ query_kernel(QueryArgs a)
 
     const int kc = s_kcur;
     if (a.split > 1) {
-        // this share's top-k (entries past it are ~0, which sort last) for
-        // the merge kernel; every share counted the same candidates
+        // this share's top-k (entries past it are ~0, which sort last) and its
+        // count of distinct candidates, for the merge kernel
         uint64_t *mp = a.part + ((int64_t)q * a.split + share) * a.k;
         for (int r = tid; r < a.k; r += QT)
             mp[r] = r < kc ? topk[r] : ~0ull;
-        if (tid == 0 && share == 0 && a.ncand)
-            a.ncand[q] = (int32_t)s_ncand;
+        if (tid == 0)
+            a.pcount[(int64_t)q * a.split + share] = s_ncand;
         return;
     }
     for (int r = tid; r < a.k; r += QT) {
@@ -925,15 +933,25 @@ query_kernel(QueryArgs a)
 }
 
 // The k best of a query's split * k share entries (distinct, except the ~0
-// padding): entry i goes to rank #{j : e_j < e_i, or e_j == e_i and j < i}.
-// One workgroup per query, one thread per entry (split * k <= 256).
-__global__ __launch_bounds__(256) void query_merge_kernel(const uint64_t *part, int split, int k,
-                                                          int64_t *ids, float *score)
+// padding: the shares hold disjoint ids): entry i goes to rank
+// #{j : e_j < e_i, or e_j == e_i and j < i}.  The query's candidate count is
+// the sum of the shares'.  One workgroup per query, one thread per entry
+// (split * k <= 256).
+__global__ __launch_bounds__(256) void query_merge_kernel(const uint64_t *part,
+                                                          const uint32_t *pcount, int split, int k,
+                                                          int64_t *ids, float *score,
+                                                          int32_t *ncand)
 {
     __shared__ uint64_t e[kQuerySplit * kMaxK];
     const int q = blockIdx.x, n = split * k, i = threadIdx.x;
     if (i < n)
         e[i] = part[(int64_t)q * n + i];
+    if (i == 0 && ncand) {
+        uint32_t c = 0;
+        for (int j = 0; j < split; ++j)
+            c += pcount[(int64_t)q * split + j];
+        ncand[q] = (int32_t)c;
+    }
     __syncthreads();
     if (i >= n)
         return;
@@ -949,12 +967,13 @@ __global__ __launch_bounds__(256) void query_merge_kernel(const uint64_t *part, 
     }
 }
 
-// Workspace of a split batch: the shares' top-k lists [nq][kQuerySplit][k].
+// Workspace of a split batch: the shares' top-k lists [nq][kQuerySplit][k],
+// then their candidate counts [nq][kQuerySplit].
 size_t query_ws_bytes(int64_t nq, int32_t k)
 {
     if (nq < 1 || nq > kSplitQueries || k < 1 || k > kMaxK)
         return 0;
-    return (size_t)nq * kQuerySplit * (size_t)k * 8;
+    return (size_t)nq * kQuerySplit * ((size_t)k * 8 + 4);
 }
 
 } // namespace lsh
@@ -1058,6 +1077,7 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
         // either way and gain from halving their heaviest queries' scoring
         a.split = Q->n <= cus ? (int32_t)std::min<int64_t>(kQuerySplit, cus / Q->n) : 2;
         a.part = (uint64_t *)workspace;
+        a.pcount = (uint32_t *)(a.part + (size_t)Q->n * kQuerySplit * k);
     }
     const int64_t nwg = Q->n * a.split;
     const bool solo = nwg <= cus;
@@ -1076,7 +1096,8 @@ extern "C" lsh_status lsh_query(const lsh_index *const *segs, int32_t nseg, cons
     LSH_LAUNCHED("query_kernel");
     if (a.split > 1) {
         hipLaunchKernelGGL(query_merge_kernel, dim3((unsigned)Q->n), dim3(256), 0,
-                           (hipStream_t)stream, (const uint64_t *)a.part, a.split, k, ids, score);
+                           (hipStream_t)stream, (const uint64_t *)a.part,
+                           (const uint32_t *)a.pcount, a.split, k, ids, score, ncand);
         LSH_LAUNCHED("query_merge_kernel");
     }
     return LSH_OK;
