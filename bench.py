@@ -597,9 +597,16 @@ def precision_path(torch, lsh, dev):
         q = (X / scale[:, None]).clamp(-qmax, qmax).to(dt)
         bytes_pp = d * esz + 4 + 8 * L
         e = {}
-        for rc in (False, True):
+        # recheck 2: the workspace already holds the recheck's table of h (a
+        # server's calls after its first)
+        ws = torch.empty(lsh.lib().lsh_hash_workspace_bytes(d, K * L, 1), dtype=torch.uint8,
+                         device=dev)
+        lsh.lsh_hash_cs(q[:1], hd, sd, family=0, K=K, L=L, w=w, b=b, scale=scale[:1], recheck=1,
+                        ws=ws)
+        for rc, key in ((0, "fast"), (1, "recheck"), (2, "recheck_table_kept")):
             fn = lambda c=None: lsh.lsh_hash_cs(q, hd, sd, family=0, K=K, L=L, w=w, b=b,
-                                                scale=scale, recheck=rc, counters=c)
+                                                scale=scale, recheck=rc, counters=c,
+                                                ws=ws if rc == 2 else None)
             for _ in range(2):
                 fn()
             torch.cuda.synchronize()
@@ -607,7 +614,7 @@ def precision_path(torch, lsh, dev):
             c = torch.zeros(4, dtype=torch.int64, device=dev)
             fn(c)
             cnt = c.cpu().numpy()
-            e["recheck" if rc else "fast"] = {
+            e[key] = {
                 "ms": round(med, 4), "gbs": round(n * bytes_pp / (med * 1e-3) / 1e9, 1),
                 **({"recomputed": int(cnt[0]), "changed": int(cnt[1]),
                     "changed_per_million_codes": round(cnt[1] / (n * K * L) * 1e6, 3)} if rc

@@ -103,7 +103,12 @@ typedef struct lsh_disc {
                          within a rigorous bound of its error from a bin edge
                          (E2LSH) or from zero (SRP) is recomputed in FP64 in
                          ascending coordinate order, so codes equal those of an
-                         FP64 evaluation.  CS/HCS only; needs d <= 32768. */
+                         FP64 evaluation.  CS/HCS only; needs d <= 32768.
+                         2: as 1, with the recheck's table (the CSR of h)
+                         that an earlier call with recheck = 1 built in the
+                         same workspace for the same h (or h_k), d and m, in
+                         stream order: the call does not build it again.
+                         lsh_hash_cs_noalloc refuses 2. */
     const uint32_t *comp_slot; /* [m] device array or NULL (CS/HCS only).  Sketch
                          component l is written to code position comp_slot[l],
                          i.e. component comp_slot[l] % K of table
@@ -171,7 +176,7 @@ lsh_status lsh_quantize_rows(const float *x, int64_t n, int32_t d, int64_t ldx, 
 
 /* ---------------------------------------------------------------- hashing */
 
-/* Workspace bytes for lsh_hash_cs / lsh_hash_hcs (0 unless recheck = 1). */
+/* Workspace bytes for lsh_hash_cs / lsh_hash_hcs (0 unless recheck is 1 or 2). */
 size_t lsh_hash_workspace_bytes(int32_t d, int32_t m, int32_t recheck);
 
 /* CS-E2LSH / CS-SRP of every point (Definitions CS_Eucl_LSH and

@@ -1450,6 +1450,8 @@ lsh_status check_disc(const lsh_disc *c)
         if (!c->b)
             LSH_FAIL(LSH_EINVAL, "E2LSH needs the shift vector b");
     }
+    if (c->recheck < 0 || c->recheck > 2)
+        LSH_FAIL(LSH_EINVAL, "recheck must be 0, 1 or 2 (got %d)", c->recheck);
     return LSH_OK;
 }
 
@@ -1614,16 +1616,19 @@ static lsh_status hash_common(const lsh_points *pts, HashArgs a, const lsh_disc 
         int p2 = 1;
         while (p2 < pts->d)
             p2 <<= 1;
-        // the rank-sort path keeps counts and list in LDS when they fit
-        const size_t list_words = (size_t)a.m + 1 + (size_t)pts->d;
-        const size_t lds_words =
-            list_words * 4 <= 160 * 1024 ? std::max((size_t)p2, list_words) : (size_t)p2;
-        const size_t clds = lds_words * 4;
-        LSH_HIP(hipFuncSetAttribute((const void *)csr_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)clds));
-        hipLaunchKernelGGL(csr_kernel, dim3(1), dim3(kCsrThreads), clds, s, a, (uint32_t *)a.csr_off,
-                           (uint32_t *)a.csr_idx, cmax_ws, p2, (int)lds_words);
-        LSH_LAUNCHED("csr_kernel");
+        // recheck = 2: the workspace holds this table's CSR from an earlier call
+        if (disc->recheck == 1) {
+            // the rank-sort path keeps counts and list in LDS when they fit
+            const size_t list_words = (size_t)a.m + 1 + (size_t)pts->d;
+            const size_t lds_words =
+                list_words * 4 <= 160 * 1024 ? std::max((size_t)p2, list_words) : (size_t)p2;
+            const size_t clds = lds_words * 4;
+            LSH_HIP(hipFuncSetAttribute((const void *)csr_kernel,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)clds));
+            hipLaunchKernelGGL(csr_kernel, dim3(1), dim3(kCsrThreads), clds, s, a, (uint32_t *)a.csr_off,
+                               (uint32_t *)a.csr_idx, cmax_ws, p2, (int)lds_words);
+            LSH_LAUNCHED("csr_kernel");
+        }
     }
 
     e = launch_hash(false);
@@ -1703,6 +1708,9 @@ extern "C" lsh_status lsh_hash_cs_noalloc(const lsh_points *pts, const uint32_t 
         LSH_FAIL(LSH_EINVAL, "points and discretisation descriptors are required");
     void *ws = nullptr;
     size_t wsb = 0;
+    if (disc->recheck == 2)
+        LSH_FAIL(LSH_EINVAL, "recheck = 2 needs a workspace of the caller's (the static array is "
+                             "shared by every call on the GPU)");
     if (disc->recheck) {
         if (pts->d < 1 || pts->d > lsh::kCsrMaxD || disc->m < 1 || disc->m > 16384)
             LSH_FAIL(LSH_EINVAL,

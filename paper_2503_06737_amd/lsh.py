@@ -166,17 +166,28 @@ def _outputs(n, m, L, device, keys, codes, proj, counters):
     return o, out
 
 
+def _hash_ws(x, m, recheck, ws):
+    """The recheck's workspace: the caller's (recheck = 2 reuses the table an
+    earlier call built in it) or a new one."""
+    wsb = lib().lsh_hash_workspace_bytes(x.shape[1], m, int(recheck))
+    if ws is None:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=x.device)
+    elif ws.numel() < wsb:
+        raise ValueError(f"hash workspace needs {wsb} bytes, got {ws.numel()}")
+    return ws, wsb
+
+
 def lsh_hash_cs(x, h, s, *, family, K, L, w=1.0, b=None, scale=None, recheck=False, keys=True,
-                codes=False, proj=False, counters=None, comp_slot=None):
+                codes=False, proj=False, counters=None, comp_slot=None, ws=None):
     """CS-E2LSH / CS-SRP of the rows of x.  Returns dict(keys [L][n] int64 bit
     patterns of the u64 keys, codes [n][m], proj [n][m], counters).
     comp_slot: optional [m] device tensor, the code position of each sketch
-    component (a permutation of range(m))."""
+    component (a permutation of range(m)).  recheck: 0, 1 or 2 (2: reuse the
+    recheck table a call with recheck = 1 built in ws for the same h, d, m)."""
     pts = points(x, scale)
     m = K * L
     o, out = _outputs(x.shape[0], m, L, x.device, keys, codes, proj, counters)
-    wsb = lib().lsh_hash_workspace_bytes(x.shape[1], m, int(recheck))
-    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=x.device)
+    ws, wsb = _hash_ws(x, m, recheck, ws)
     disc = _disc(family, K, L, w, b, recheck, comp_slot)
     _check(lib().lsh_hash_cs(C.byref(pts), _ptr(h), _ptr(s), C.byref(disc), C.byref(out),
                              _ptr(ws), wsb, _stream()))
@@ -200,7 +211,7 @@ def lsh_hash_cs_noalloc(x, h, s, out, *, family, K, L, w=1.0, b=None, scale=None
 
 
 def lsh_hash_hcs(x, dk, mk, hk, sk, *, family, K, L, w=1.0, b=None, scale=None, recheck=False,
-                 keys=True, codes=False, proj=False, counters=None, comp_slot=None):
+                 keys=True, codes=False, proj=False, counters=None, comp_slot=None, ws=None):
     """HCS-E2LSH / HCS-SRP.  hk/sk: device tensors with the per-mode tables back
     to back; comp_slot as for lsh_hash_cs."""
     pts = points(x, scale)
@@ -210,8 +221,7 @@ def lsh_hash_hcs(x, dk, mk, hk, sk, *, family, K, L, w=1.0, b=None, scale=None, 
     N = len(dk)
     dka = (C.c_int32 * N)(*dk)
     mka = (C.c_int32 * N)(*mk)
-    wsb = lib().lsh_hash_workspace_bytes(x.shape[1], m, int(recheck))
-    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=x.device)
+    ws, wsb = _hash_ws(x, m, recheck, ws)
     disc = _disc(family, K, L, w, b, recheck, comp_slot)
     _check(lib().lsh_hash_hcs(C.byref(pts), N, dka, mka, _ptr(hk), _ptr(sk), C.byref(disc),
                               C.byref(out), _ptr(ws), wsb, _stream()))

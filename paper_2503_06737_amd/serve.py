@@ -223,6 +223,7 @@ class Server:
         dev = base.device
         self.device = dev
         self.recheck = recheck
+        self._hash_ws = {}  # stream -> recheck workspace holding the table of h
         self.storage = storage
         self.d = base.shape[1]
         self.K, self.L, self.w, self.k, self.metric = K, L, w, k, metric
@@ -255,9 +256,21 @@ class Server:
         return self.base[lo:hi], None if self.scale is None else self.scale[lo:hi]
 
     def _hash(self, x: torch.Tensor, scale=None) -> torch.Tensor:
+        # With the recheck, each stream keeps its workspace: the first call on
+        # it builds the recheck's table of h there, later calls reuse it
+        # (calls on one stream run in order).
+        ws, mode = None, 0
+        if self.recheck:
+            st = torch.cuda.current_stream().cuda_stream
+            ws = self._hash_ws.get(st)
+            mode = 2 if ws is not None else 1
+            if ws is None:
+                nb = lsh.lib().lsh_hash_workspace_bytes(x.shape[1], self.K * self.L, 1)
+                ws = self._hash_ws[st] = torch.empty(max(nb, 1), dtype=torch.uint8,
+                                                     device=x.device)
         return lsh.lsh_hash_cs(x, self.h, self.s, family=self.metric, K=self.K, L=self.L,
                                w=self.w, b=self.b if self.metric == lsh.E2LSH else None,
-                               scale=scale, recheck=self.recheck)["keys"]
+                               scale=scale, recheck=mode, ws=ws)["keys"]
 
     def _build(self, keys: torch.Tensor, id_base: int, checks: list) -> lsh.Index:
         idx = lsh.lsh_build_index(keys, id_base=id_base)

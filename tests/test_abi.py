@@ -48,6 +48,14 @@ def test_library_argument_errors_need_no_gpu():
     st = L.lsh_hash_cs(C.byref(pts), C.c_void_p(1), C.c_void_p(1), C.byref(disc), C.byref(out),
                        None, 0, None)
     assert st == -1 and b"m = K*L" in L.lsh_last_error()
+    disc = lsh.Disc(0, 8, 4, 2, 1.0, C.c_void_p(16), 3)  # recheck outside 0..2
+    st = L.lsh_hash_cs(C.byref(pts), C.c_void_p(1), C.c_void_p(1), C.byref(disc), C.byref(out),
+                       None, 0, None)
+    assert st == -1 and b"recheck" in L.lsh_last_error()
+    disc = lsh.Disc(0, 8, 4, 2, 1.0, C.c_void_p(16), 2)  # reuse needs the caller's workspace
+    st = L.lsh_hash_cs_noalloc(C.byref(pts), C.c_void_p(1), C.c_void_p(1), C.byref(disc),
+                               C.byref(out), None)
+    assert st == -1 and b"recheck = 2" in L.lsh_last_error()
     h = C.c_void_p()
     st = L.lsh_build_index(C.c_void_p(256), 0, 10, 2, (1 << 32) - 5, C.c_void_p(256), 1 << 20,
                            C.c_void_p(256), 1 << 20, C.byref(h), None, None)

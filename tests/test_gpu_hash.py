@@ -483,3 +483,48 @@ def test_recheck_bin_table_every_path(heavy, family):
                           b=to_dev(b), codes=True, recheck=True, counters=cnt)
     compare_hash(out, ref, x64, K, L, exact=True, what=f"bin table heavy={heavy}")
     assert int(to_host(cnt, np.uint64)[0]) > 0
+
+
+@pytest.mark.parametrize("family", [oracle.E2LSH, oracle.SRP])
+def test_recheck_reuses_the_table_in_its_workspace(family):
+    """recheck = 2 reuses the table (CSR of h) that a recheck = 1 call built in
+    the same workspace: codes, keys and counters equal those of recheck = 1,
+    for CS on BF16 rows and for HCS (N = 2) on FP32 rows, over several calls
+    on other rows; the codes equal the FP64 oracle's."""
+    dev()
+    import torch
+    K, L = 16, 32
+    d = 4096
+    x = synth.gaussian_clusters(900, d, 10, 0.1, 41)
+    q, sc = synth.quantise_rows(x, "bf16")
+    x64 = oracle.decode(q, sc)
+    h, s = synth.cs_state(d, K * L, 42)
+    b = synth.shifts(K * L, 4.0, 42)
+    kw = dict(family=family, K=K, L=L, w=4.0, b=to_dev(b), codes=True)
+    ws = torch.empty(lsh.lib().lsh_hash_workspace_bytes(d, K * L, 1), dtype=torch.uint8,
+                     device=dev())
+    qd, sd_ = to_dev(q), to_dev(sc)
+    for i, (lo, hi) in enumerate(((0, 300), (300, 700), (700, 900))):
+        c1, c2 = to_dev(np.zeros(4, np.uint64)), to_dev(np.zeros(4, np.uint64))
+        one = lsh.lsh_hash_cs(qd[lo:hi], to_dev(h), to_dev(s), scale=sd_[lo:hi], recheck=1,
+                              counters=c1, **kw)
+        two = lsh.lsh_hash_cs(qd[lo:hi], to_dev(h), to_dev(s), scale=sd_[lo:hi],
+                              recheck=1 if i == 0 else 2, ws=ws, counters=c2, **kw)
+        for key in ("keys", "codes"):
+            assert torch.equal(one[key], two[key]), (i, key)
+        assert (to_host(c1, np.uint64) == to_host(c2, np.uint64)).all()
+    ref = oracle.hash_points(x64[700:900], family, K, L, kind="cs", w=4.0, b=b, h=h, s=s)
+    assert (to_host(two["codes"]) == ref["codes"]).all()
+    # HCS N = 2 (64 x 64 -> 16 x 32), FP32 rows
+    dk, mk = (64, 64), (16, 32)
+    hk, sk = synth.hcs_state(dk, mk, 43)
+    hkd, skd = to_dev(np.concatenate(hk)), to_dev(np.concatenate(sk))
+    xd = to_dev(x)
+    ws2 = torch.empty(lsh.lib().lsh_hash_workspace_bytes(d, K * L, 1), dtype=torch.uint8,
+                      device=dev())
+    for i, (lo, hi) in enumerate(((0, 450), (450, 900))):
+        one = lsh.lsh_hash_hcs(xd[lo:hi], dk, mk, hkd, skd, recheck=1, **kw)
+        two = lsh.lsh_hash_hcs(xd[lo:hi], dk, mk, hkd, skd, recheck=1 if i == 0 else 2, ws=ws2,
+                               **kw)
+        for key in ("keys", "codes"):
+            assert torch.equal(one[key], two[key]), (i, key)
