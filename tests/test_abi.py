@@ -61,3 +61,16 @@ def test_library_argument_errors_need_no_gpu():
                            C.c_void_p(256), 1 << 20, C.byref(h), None, None)
     assert st == -5
     assert L.lsh_index_bytes(1000, 4) >= 1000 * 4 * 16
+
+
+def test_query_workspace_sizes_need_no_gpu():
+    """lsh_query_workspace_bytes: the shares' top-k lists and counts for 1..1024
+    queries (four shares at most), 0 outside that range or for k outside 1..64."""
+    from paper_2503_06737_amd import lsh
+    if not os.path.exists(lsh.LIB_PATH):
+        pytest.skip("liblsh.so not built")
+    L = lsh.lib()
+    assert L.lsh_query_workspace_bytes(1, 10) == 4 * (10 * 8 + 4)
+    assert L.lsh_query_workspace_bytes(1024, 64) == 1024 * 4 * (64 * 8 + 4)
+    for nq, k in ((0, 10), (1025, 10), (10, 0), (10, 65), (-1, 10)):
+        assert L.lsh_query_workspace_bytes(nq, k) == 0, (nq, k)
