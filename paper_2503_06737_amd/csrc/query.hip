@@ -6,13 +6,20 @@
 // query (Euclidean, or 1 - cos), and keep the k best by (score, id)
 // (Section 6 retrieves the top-k this way).
 //
-// One workgroup per query.  Every bucket is an ascending id list, so the
-// union is processed in windows of the id space that hold at most 2048 (a
-// query alone) or 1024 (in a batch) (bucket, id) entries: each window is
-// gathered into LDS, sorted and deduplicated, its distinct ids are scored
-// (one wave per candidate row, coalesced loads), and the window's (score,
-// id) pairs are merged with the running top-k by a bitonic sort of 64-bit
-// (score bits, id) keys.  Memory is bounded whatever the bucket sizes.
+// One workgroup per query (or per share, below).  Every bucket is an
+// ascending id list, so the union is processed in windows of the id space
+// that hold at most 2048 (one workgroup per CU) or 1024 (more) (bucket, id)
+// entries: each window is gathered into LDS, sorted and deduplicated, its
+// distinct ids are scored (one wave per candidate row, coalesced loads), and
+// the window's (score, id) pairs are merged with the running top-k by a
+// bitonic sort of 64-bit (score bits, id) keys.  Memory is bounded whatever
+// the bucket sizes.
+//
+// Given a workspace, a batch of at most 1024 queries splits each query over
+// several workgroups that take the candidate ids of their residue (id mod
+// split): each bounds the same windows but gathers, sorts, dedupes and scores
+// only its own ids, and leaves its top-k and candidate count in the
+// workspace; query_merge_kernel then ranks the shares' entries per query.
 
 #include <math.h>
 
